@@ -1,0 +1,229 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) WCSPH hot path.
+ *
+ * The library runs one time step of a weakly compressible SPH dam break, or
+ * many independent ones batched into the same launches, on one GPU:
+ *
+ *   cell keys -> stable radix sort of particles by cell -> cell start table
+ *   (the cell linked list, direct search over the nearest cells and radix
+ *   sort of the paper's Sec. 5) -> density summation sweep -> pressure and
+ *   viscous force sweep -> kick-drift-kick ("two half") time integration and
+ *   the FP64 reductions that give the CFL time step and the conservation
+ *   diagnostics.
+ *
+ * Formulation, per fluid particle i over neighbours j (fluid or fixed wall
+ * particles within 2h, found in the 3^d cells around i; the paper leaves the
+ * discretisation unstated, the one below is the textbook WCSPH):
+ *   W(r) = a_d (1-q/2)^4 (2q+1), q = r/h (Wendland C2), grad_i W = F(r) r_ij,
+ *   F(r) = -5 a_d (1-q/2)^3 / h^2, a_2 = 7/(4 pi h^2), a_3 = 21/(16 pi h^3);
+ *   sigma0 = sum over the lattice Z^d dx of W, m = rho0 / sigma0;
+ *   rho_sum = m (W(0) + sum_j W_ij),  rho* = rho + dt sum_j m v_ij.F r_ij,
+ *   rho <- rho_sum + max(0, rho* - rho_sum) rho0 / rho*,
+ *   p = max(0, c0^2 (rho - rho0)), P = p / rho^2;
+ *   a_i = g - sum_j m (P_i + P_j + Pi_ij) F_ij r_ij, Pi_ij the Monaghan
+ *   artificial viscosity -alpha c0 h v_ij.r_ij / (rhobar (r^2 + eps h^2)) on
+ *   approach; a wall j carries rho_j = rho_i, v_j = 0 and the hydrostatic
+ *   mirror p_j = max(0, p_i + rho_i g.(x_j - x_i));
+ *   step: v += dt/2 a; x += dt v; cells; sweeps; v += dt/2 a;
+ *   dt <- min(C_ac h / (c0 + max|v|), C_f sqrt(h / max|a|)) per instance.
+ *
+ * Conventions
+ *   - Every call returns an sph_status; no exception crosses the ABI.  A
+ *     failed call leaves a message in sph_last_error() (per host thread).
+ *   - Device pointers are caller-owned (allocated by the caller, e.g. torch).
+ *     The library allocates no device memory: scratch lives in the caller's
+ *     workspace of sph_workspace_size() bytes.  Pointers passed to sph_bind
+ *     must stay valid until sph_destroy or the next sph_bind.
+ *   - Stage calls are stream-ordered and asynchronous; argument errors are
+ *     reported synchronously; device-side conditions set sticky flags read by
+ *     sph_poll_errors.  One context per stream / host thread at a time.
+ *   - Per-particle arrays are structure-of-arrays, component-major: component
+ *     a of particle i of an array with n particles sits at [a * n + i].
+ *     Instances are concatenated in order (instance b's fluid particles occupy
+ *     storage slots [fluid_offset(b), fluid_offset(b+1)), likewise walls).
+ *   - Units are SI.  Indices are int32.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_E_ARG = -1,          /* invalid argument (checked on the host) */
+    SPH_E_STATE = -2,        /* call out of order (e.g. step before bind/prime) */
+    SPH_E_HIP = -3,          /* a HIP runtime call failed */
+    SPH_E_CAPACITY = -4,     /* a size exceeds what the library supports */
+    SPH_E_UNSUPPORTED = -5   /* option not available */
+} sph_status;
+
+typedef enum {
+    SPH_FP64 = 0,            /* all arithmetic in FP64 */
+    SPH_MIXED = 1            /* FP32 pair sweeps on FP32 offsets from FP64 cell
+                                origins; FP64 state, integration and reductions */
+} sph_precision;
+
+/* Per-instance diagnostics, SPH_NDIAG doubles per instance, written by the
+ * reductions after every step (and by sph_prime):
+ *  0 max|v|   1 max|a|   2 fluid mass   3..5 momentum sum m v
+ *  6 kinetic energy   7 potential energy -sum m g.x
+ *  8 internal energy sum m c0^2 (ln(rho/rho0) + rho0/rho - 1) over rho > rho0
+ *  9 |sum m a_ff|, the fluid-fluid force residual of the step (0 exactly)
+ * 10 mean(rho)/rho0 - 1   11 clamped cell keys (cumulative)
+ * 12 neighbour pairs of the step (sum of counts)
+ * 13 cumulative sum of dt |sum m a_ff|   14 simulated time   15 steps done */
+#define SPH_NDIAG 16
+
+/* Sticky device flags returned by sph_poll_errors. */
+#define SPH_FLAG_CLAMPED   1u   /* a particle left the grid; its key was clamped */
+#define SPH_FLAG_NONFINITE 2u   /* a reduction saw a non-finite max|v| or max|a| */
+#define SPH_FLAG_CAPACITY  4u   /* a per-target work list overflowed (handled) */
+
+typedef struct {
+    int32_t n_fluid;         /* fluid particles of this instance (>= 0) */
+    int32_t n_wall;          /* fixed wall particles of this instance (>= 0) */
+    double tank_lo[3];       /* lower corner of the tank interior (unused axes 0) */
+    double tank_hi[3];       /* upper corner of the tank interior */
+    double c0;               /* artificial sound speed of this instance */
+} sph_instance_desc;
+
+typedef struct {
+    int32_t dim;             /* 2 or 3; gravity acts along the last axis */
+    int32_t precision;       /* sph_precision */
+    int32_t n_instances;     /* >= 1 */
+    int32_t reorder_every;   /* K: physical reorder of the arrays by cell every K
+                                steps (0 = never); the cell table itself is
+                                rebuilt every step */
+    double dx;               /* lattice spacing of the initial particles */
+    double h;                /* smoothing length; support and cell size are 2h */
+    double rho0;             /* reference density */
+    double alpha;            /* artificial viscosity coefficient */
+    double eps;              /* viscosity regulariser (times h^2) */
+    double cfl_ac;           /* acoustic/advective Courant number */
+    double cfl_f;            /* body-force Courant number */
+    double g[3];             /* gravity */
+    const sph_instance_desc *inst;   /* n_instances entries (copied) */
+    int32_t block_threads;   /* threads per sweep block: 0 (default 256), 64, 128, 256 */
+    int32_t queue_cap;       /* per-thread neighbour queue of the sweeps: 0 = default */
+    int32_t use_graph;       /* sph_step_batched replays captured HIP graphs */
+    int32_t reserved[5];
+} sph_params;
+
+typedef struct {
+    /* fluid, storage order, N = sum of n_fluid */
+    double *x;               /* [dim*N] positions */
+    double *v;               /* [dim*N] velocities */
+    double *a;               /* [dim*N] accelerations */
+    double *rho;             /* [N] densities */
+    int32_t *id;             /* [N] particle ids, reordered with the data */
+    int32_t *key;            /* [N] cell key of each particle (out) */
+    int32_t *perm;           /* [N] sorted slot k -> storage index (out) */
+    int32_t *count;          /* [N] neighbour count of each particle (out) */
+    /* walls, fixed; Nw = sum of n_wall */
+    const double *xw;        /* [dim*Nw] wall particle centres (read at bind) */
+    int32_t *wall_perm;      /* [Nw] wall sorted slot -> wall index (out, at bind) */
+    /* cell tables over all instances, C = sum of cells (sph_get_info) */
+    int32_t *cell_start;     /* [C+1] fluid: cell c holds sorted slots
+                                cell_start[c] .. cell_start[c+1]-1 */
+    int32_t *wall_start;     /* [C+1] walls, same convention (out, at bind) */
+    /* per instance */
+    double *dt;              /* [B] time step of the next step */
+    double *diag;            /* [B*SPH_NDIAG] */
+    /* scratch */
+    void *workspace;         /* sph_workspace_size() bytes, 256-byte aligned */
+} sph_buffers;
+
+typedef struct {
+    int64_t n_fluid;         /* N */
+    int64_t n_wall;          /* Nw */
+    int64_t n_cells;         /* C */
+    size_t workspace_bytes;
+    double sigma0;           /* lattice number density (1/m^d) */
+    double mass;             /* particle mass rho0/sigma0 */
+    double cell_size;        /* 2h */
+    int64_t steps_done;      /* steps since sph_prime */
+} sph_info;
+
+typedef struct sph_ctx sph_ctx;
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *sph_last_error(void);
+
+/* Validate and copy the parameters; derive sigma0, the particle mass, the cell
+ * grid of every instance (origin tank_lo - 3 dx, ceil((tank extent + 6 dx)/2h)
+ * cells per axis, x fastest) and the workspace layout.  No device memory is
+ * touched.  On success *out owns a context to be released by sph_destroy. */
+sph_status sph_create(const sph_params *p, sph_ctx **out);
+
+/* Release the context and anything the library owns (host objects, graphs,
+ * events); caller memory is never freed.  NULL is accepted. */
+void sph_destroy(sph_ctx *ctx);
+
+/* Sizes derived by sph_create. */
+sph_status sph_get_info(const sph_ctx *ctx, sph_info *info);
+
+/* Grid of instance b: origin lo[3], cells per axis ncell[3] and the offset of
+ * its first cell in the global cell numbering (its keys are local + base). */
+sph_status sph_get_grid(const sph_ctx *ctx, int32_t b, double lo[3], int32_t ncell[3],
+                        int32_t *cell_base);
+
+/* Workspace bytes the caller must allocate and pass in sph_buffers. */
+sph_status sph_workspace_size(const sph_ctx *ctx, size_t *bytes);
+
+/* Attach caller buffers (all device pointers) and build the static wall cell
+ * table: wall keys, the stable sort of walls by cell (wall_perm), wall_start
+ * and the sorted wall records.  Synchronises `stream` before returning. */
+sph_status sph_bind(sph_ctx *ctx, const sph_buffers *b, void *stream);
+
+/* Step 0: cell table at the current positions, density with dt = 0 (so
+ * rho <- rho_sum + max(0, rho - rho_sum) rho0/rho), forces, reductions.  Gives
+ * a^0, dt^0 and diag; resets diag and the step counter. */
+sph_status sph_prime(sph_ctx *ctx, void *stream);
+
+/* Cell keys from the current positions (and the per-cell counts the sort
+ * consumes).  Must be followed by sph_sort before the next sph_build_cells. */
+sph_status sph_build_cells(sph_ctx *ctx, void *stream);
+
+/* Stable radix sort of storage indices by key (perm), cell_start, and the
+ * sorted sweep records.  reorder != 0 also gathers x, v, rho and id into
+ * sorted order (perm becomes the identity, key the sorted keys). */
+sph_status sph_sort(sph_ctx *ctx, int32_t reorder, void *stream);
+
+/* Density sweep: rho (storage order), neighbour counts, P.  Uses dt[]. */
+sph_status sph_density(sph_ctx *ctx, void *stream);
+
+/* Force sweep: a (storage order).  Does not kick. */
+sph_status sph_forces(sph_ctx *ctx, void *stream);
+
+/* half = 1: v += dt/2 a, x += dt v, then cell keys as sph_build_cells.
+ * half = 2: v += dt/2 a, then the reductions (dt[], diag[]). */
+sph_status sph_integrate(sph_ctx *ctx, int32_t half, void *stream);
+
+/* n_steps full steps of every instance: half 1 + keys, sort (with the reorder
+ * on steps where steps_done % K == 0), density, force fused with half 2,
+ * reductions.  dt stays on the device; asynchronous. */
+sph_status sph_step_batched(sph_ctx *ctx, int32_t n_steps, void *stream);
+
+/* Synchronise `stream`, return the sticky device flags and clear them. */
+sph_status sph_poll_errors(sph_ctx *ctx, uint32_t *flags, void *stream);
+
+/* Per-stage GPU time.  enable != 0 records HIP events around every stage of
+ * later steps (eager launches only).  sph_stage_times copies the accumulated
+ * milliseconds and launch counts of up to `n` stages (names from
+ * sph_stage_name) and, if reset != 0, clears them.  Synchronises `stream`. */
+sph_status sph_set_timing(sph_ctx *ctx, int32_t enable);
+sph_status sph_stage_times(sph_ctx *ctx, double *ms, int64_t *launches, int32_t n,
+                           int32_t reset, void *stream);
+const char *sph_stage_name(int32_t stage);
+int32_t sph_stage_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

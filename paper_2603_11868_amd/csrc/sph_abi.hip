@@ -1,0 +1,681 @@
+// C ABI of libsph (declared in include/sph.h): argument checking, derived
+// constants, the workspace layout, the chunk maps and the stage sequences.
+#include "sph.h"
+#include "sph_launch.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace sphx;
+
+namespace {
+
+thread_local std::string g_err;
+
+sph_status fail(sph_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(SPH_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+enum Stage { ST_KEYS = 0, ST_SCAN, ST_SORT, ST_REORDER, ST_PACK, ST_DENSITY, ST_FORCE, ST_REDUCE, ST_COUNT };
+const char *kStageNames[ST_COUNT] = {"keys", "cell_scan", "radix_sort", "reorder",
+                                     "pack", "density", "force", "reduce"};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Wendland C2 normalisation: W(0) for support 2h.
+double wendland_alpha(int dim, double h)
+{
+    const double pi = 3.14159265358979323846;
+    return dim == 2 ? 7.0 / (4.0 * pi * h * h) : 21.0 / (16.0 * pi * h * h * h);
+}
+
+// Number density of the perfect lattice of spacing dx: sum over Z^d of W(|k| dx).
+double lattice_number_density(int dim, double dx, double h)
+{
+    const double a = wendland_alpha(dim, h);
+    const int K = (int)std::ceil(2.0 * h / dx) + 1;
+    double s = 0.0;
+    const int kz0 = dim == 3 ? -K : 0, kz1 = dim == 3 ? K : 0;
+    for (int kz = kz0; kz <= kz1; ++kz)
+        for (int ky = -K; ky <= K; ++ky)
+            for (int kx = -K; kx <= K; ++kx) {
+                const double r = dx * std::sqrt((double)(kx * kx + ky * ky + kz * kz));
+                const double q = r / h;
+                if (q >= 2.0) continue;
+                const double t = 1.0 - 0.5 * q;
+                s += a * t * t * t * t * (2.0 * q + 1.0);
+            }
+    return s;
+}
+
+// Grid of one instance: origin tank_lo - 3 dx, ceil((extent + 6 dx) / cs) cells.
+void instance_grid(const sph_instance_desc &d, int dim, double dx, double cs, double lo[3],
+                   int ncell[3])
+{
+#pragma clang fp contract(off)
+    for (int a = 0; a < 3; ++a) {
+        if (a < dim) {
+            lo[a] = d.tank_lo[a] - 3.0 * dx;
+            const double ext = (d.tank_hi[a] - d.tank_lo[a]) + 6.0 * dx;
+            ncell[a] = (int)std::ceil(ext / cs);
+            if (ncell[a] < 1) ncell[a] = 1;
+        } else {
+            lo[a] = 0.0;
+            ncell[a] = 1;
+        }
+    }
+}
+
+}  // namespace
+
+struct sph_ctx {
+    sph_params p{};
+    std::vector<sph_instance_desc> inst;
+    SimConst sc{};
+    std::vector<InstDev> idev;
+    std::vector<Chunk> fmap, wmap;
+    int64_t N = 0, Nw = 0, C = 0;
+    int block = 256;
+    bool mixed = false;
+    // workspace layout (byte offsets)
+    size_t ws_bytes = 0;
+    size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec, o_pos, o_vel, o_rp,
+        o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc;
+    // state
+    bool bound = false, primed = false, cells_built = false;
+    sph_buffers buf{};
+    Dev dev{};
+    int64_t steps_done = 0;
+    // graphs
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // timing
+    bool timing = false;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double stage_ms[ST_COUNT] = {0};
+    int64_t stage_n[ST_COUNT] = {0};
+};
+
+namespace {
+
+hipEvent_t take_event(sph_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct StageTimer {
+    sph_ctx *c;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageTimer(sph_ctx *c_, int st, hipStream_t s_, bool on) : c(c_), stage(st), s(s_)
+    {
+        if (on) {
+            a = take_event(c);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~StageTimer()
+    {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        c->pending.push_back({stage, a, b});
+    }
+};
+
+void collect_times(sph_ctx *c)
+{
+    for (auto &r : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            c->stage_ms[r.stage] += ms;
+            c->stage_n[r.stage] += 1;
+        }
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->pending.clear();
+}
+
+int rec_pos_bytes(int dim, bool mixed) { return mixed ? (dim == 3 ? 16 : 8) : (dim == 3 ? 32 : 16); }
+int rec_rp_bytes(bool mixed) { return mixed ? 8 : 16; }
+
+void build_layout(sph_ctx *c)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const int64_t nmax = std::max<int64_t>(std::max<int64_t>(c->N, c->Nw), 1);
+    const int dim = c->p.dim;
+    c->o_skey = take(sizeof(int) * std::max<int64_t>(c->N, 1));
+    c->o_rk0 = take(sizeof(int) * nmax);
+    c->o_rv0 = take(sizeof(int) * nmax);
+    c->o_rk1 = take(sizeof(int) * nmax);
+    c->o_rv1 = take(sizeof(int) * nmax);
+    c->o_hist = take(sizeof(int) * 256 * (size_t)radix_tiles(nmax));
+    c->o_part = take(sizeof(int) * 16384);
+    c->o_cnt = take(sizeof(int) * (c->C + 1));
+    const size_t nf = (size_t)std::max<int64_t>(c->N, 1);
+    const size_t rec_bytes = align256(nf * rec_pos_bytes(dim, c->mixed)) * 2 + align256(nf * rec_rp_bytes(c->mixed));
+    const size_t scr_bytes = nf * sizeof(double) * (2 * dim + 2);
+    c->o_rec = take(std::max(rec_bytes, scr_bytes));
+    c->o_pos = c->o_rec;
+    c->o_vel = c->o_pos + align256(nf * rec_pos_bytes(dim, c->mixed));
+    c->o_rp = c->o_vel + align256(nf * rec_pos_bytes(dim, c->mixed));
+    c->o_wpos = take((size_t)std::max<int64_t>(c->Nw, 1) * rec_pos_bytes(dim, c->mixed));
+    c->o_wkey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
+    c->o_wskey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
+    c->o_partials = take(sizeof(double) * kNPart * std::max<size_t>(c->fmap.size(), 1));
+    c->o_fmap = take(sizeof(Chunk) * std::max<size_t>(c->fmap.size(), 1));
+    c->o_wmap = take(sizeof(Chunk) * std::max<size_t>(c->wmap.size(), 1));
+    c->o_inst = take(sizeof(InstDev) * c->idev.size());
+    c->o_flags = take(64);
+    c->o_clampc = take(sizeof(int) * c->idev.size());
+    c->ws_bytes = off;
+}
+
+void build_maps(sph_ctx *c)
+{
+    c->fmap.clear();
+    c->wmap.clear();
+    int64_t fo = 0, wo = 0;
+    for (size_t b = 0; b < c->inst.size(); ++b) {
+        InstDev &I = c->idev[b];
+        I.fluid_off = (int)fo;
+        I.n_fluid = c->inst[b].n_fluid;
+        I.wall_off = (int)wo;
+        I.n_wall = c->inst[b].n_wall;
+        I.chunk_begin = (int)c->fmap.size();
+        for (int64_t s = fo; s < fo + I.n_fluid; s += c->block)
+            c->fmap.push_back({(int)b, (int)s, (int)std::min<int64_t>(s + c->block, fo + I.n_fluid), 0});
+        I.chunk_end = (int)c->fmap.size();
+        for (int64_t s = wo; s < wo + I.n_wall; s += c->block)
+            c->wmap.push_back({(int)b, (int)s, (int)std::min<int64_t>(s + c->block, wo + I.n_wall), 0});
+        fo += I.n_fluid;
+        wo += I.n_wall;
+    }
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+sph_status check_launch(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return fail(SPH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return SPH_OK;
+}
+
+#define TRY(st)                         \
+    do {                                \
+        sph_status s_ = (st);           \
+        if (s_ != SPH_OK) return s_;    \
+    } while (0)
+
+// ---- stage sequences ------------------------------------------------------
+
+sph_status do_keys(sph_ctx *c, int kick_on, hipStream_t s, bool timed)
+{
+    StageTimer t(c, ST_KEYS, s, timed);
+    return check_launch(launch_keys(c->sc, c->dev, kick_on, s), "keys");
+}
+
+sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
+{
+    const Dev &d = c->dev;
+    {
+        StageTimer t(c, ST_SCAN, s, timed);
+        TRY(check_launch(launch_exclusive_scan(d.cnt, d.cell_start, c->C + 1, d.part, 1, s), "cell scan"));
+    }
+    {
+        StageTimer t(c, ST_SORT, s, timed);
+        TRY(check_launch(launch_radix_sort(d.key, c->N, c->C, d.skey, d.perm, d.rk0, d.rv0, d.rk1,
+                                           d.rv1, d.hist, d.part, s),
+                         "radix sort"));
+    }
+    if (reorder) {
+        StageTimer t(c, ST_REORDER, s, timed);
+        TRY(check_launch(launch_reorder(c->sc, d, s), "reorder"));
+    }
+    StageTimer t(c, ST_PACK, s, timed);
+    return check_launch(launch_pack(c->sc, d, c->mixed, s), "pack");
+}
+
+sph_status do_density(sph_ctx *c, int use_dt, hipStream_t s, bool timed)
+{
+    StageTimer t(c, ST_DENSITY, s, timed);
+    return check_launch(launch_density(c->sc, c->dev, c->mixed, use_dt, s), "density");
+}
+
+sph_status do_force(sph_ctx *c, int fused, hipStream_t s, bool timed)
+{
+    StageTimer t(c, ST_FORCE, s, timed);
+    return check_launch(launch_force(c->sc, c->dev, c->mixed, fused, s), "force");
+}
+
+sph_status do_reduce(sph_ctx *c, int prime, hipStream_t s, bool timed)
+{
+    StageTimer t(c, ST_REDUCE, s, timed);
+    return check_launch(launch_final_reduce(c->sc, c->dev, prime, s), "reduce");
+}
+
+sph_status enqueue_step(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
+{
+    TRY(do_keys(c, 1, s, timed));
+    TRY(do_sort(c, reorder, s, timed));
+    TRY(do_density(c, 1, s, timed));
+    TRY(do_force(c, 1, s, timed));
+    return do_reduce(c, 0, s, timed);
+}
+
+bool reorder_due(const sph_ctx *c)
+{
+    return c->p.reorder_every > 0 && (c->steps_done % c->p.reorder_every) == 0;
+}
+
+sph_status ensure_graph(sph_ctx *c, int variant)
+{
+    if (c->gexec[variant]) return SPH_OK;
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    sph_status st = enqueue_step(c, variant == 1, c->cap_stream, false);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != SPH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(SPH_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec[variant], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec[variant] = nullptr;
+        return fail(SPH_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return SPH_OK;
+}
+
+void drop_graphs(sph_ctx *c)
+{
+    for (auto &g : c->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+}  // namespace
+
+// =========================================================================
+// ABI
+// =========================================================================
+
+extern "C" {
+
+const char *sph_last_error(void) { return g_err.c_str(); }
+
+const char *sph_stage_name(int32_t stage)
+{
+    if (stage < 0 || stage >= ST_COUNT) return "";
+    return kStageNames[stage];
+}
+
+int32_t sph_stage_count(void) { return ST_COUNT; }
+
+sph_status sph_create(const sph_params *p, sph_ctx **out)
+{
+    if (!p || !out) return fail(SPH_E_ARG, "null argument");
+    *out = nullptr;
+    if (p->dim != 2 && p->dim != 3) return fail(SPH_E_ARG, "dim must be 2 or 3");
+    if (p->precision != SPH_FP64 && p->precision != SPH_MIXED) return fail(SPH_E_ARG, "unknown precision");
+    if (p->n_instances < 1 || !p->inst) return fail(SPH_E_ARG, "need at least one instance");
+    if (p->reorder_every < 0) return fail(SPH_E_ARG, "reorder_every must be >= 0");
+    if (!(p->dx > 0.0) || !(p->h > 0.0) || !(p->rho0 > 0.0)) return fail(SPH_E_ARG, "dx, h and rho0 must be positive");
+    if (!(p->alpha >= 0.0) || !(p->eps > 0.0) || !(p->cfl_ac > 0.0) || !(p->cfl_f > 0.0))
+        return fail(SPH_E_ARG, "alpha >= 0, eps > 0 and positive Courant numbers required");
+    const int block = p->block_threads == 0 ? 256 : p->block_threads;
+    if (block != 64 && block != 128 && block != 256) return fail(SPH_E_ARG, "block_threads must be 0, 64, 128 or 256");
+    auto *c = new sph_ctx();
+    c->p = *p;
+    c->p.inst = nullptr;
+    c->block = block;
+    c->mixed = p->precision == SPH_MIXED;
+    c->inst.assign(p->inst, p->inst + p->n_instances);
+    const double cs = 2.0 * p->h;
+    int64_t N = 0, Nw = 0, C = 0;
+    c->idev.resize(c->inst.size());
+    for (size_t b = 0; b < c->inst.size(); ++b) {
+        const sph_instance_desc &d = c->inst[b];
+        if (d.n_fluid < 0 || d.n_wall < 0) { delete c; return fail(SPH_E_ARG, "negative particle count"); }
+        if (!(d.c0 > 0.0)) { delete c; return fail(SPH_E_ARG, "c0 must be positive"); }
+        for (int a = 0; a < p->dim; ++a)
+            if (!(d.tank_hi[a] > d.tank_lo[a])) { delete c; return fail(SPH_E_ARG, "empty tank"); }
+        InstDev &I = c->idev[b];
+        std::memset(&I, 0, sizeof(I));
+        instance_grid(d, p->dim, p->dx, cs, I.lo, I.ncell);
+        const int64_t nc = (int64_t)I.ncell[0] * I.ncell[1] * I.ncell[2];
+        I.cell_base = (int)std::min<int64_t>(C, INT32_MAX);
+        I.c0 = d.c0;
+        C += nc;
+        N += d.n_fluid;
+        Nw += d.n_wall;
+    }
+    if (N >= INT32_MAX || Nw >= INT32_MAX || C >= INT32_MAX - 1) { delete c; return fail(SPH_E_CAPACITY, "more than 2^31 particles or cells"); }
+    if (C + 1 > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many cells for the two-level scan"); }
+    if ((int64_t)256 * radix_tiles(std::max(N, Nw)) > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many particles for the radix histogram scan"); }
+    c->N = N;
+    c->Nw = Nw;
+    c->C = C;
+    build_maps(c);
+    // constants
+    SimConst &sc = c->sc;
+    sc.dim = p->dim;
+    sc.n_inst = p->n_instances;
+    sc.N = (int)N;
+    sc.Nw = (int)Nw;
+    sc.C = (int)C;
+    sc.h = p->h;
+    sc.inv_h = 1.0 / p->h;
+    sc.cs = cs;
+    sc.inv_cs = 1.0 / cs;
+    sc.cut2 = cs * cs;
+    sc.rho0 = p->rho0;
+    sc.sigma0 = lattice_number_density(p->dim, p->dx, p->h);
+    sc.mass = p->rho0 / sc.sigma0;
+    sc.alpha = p->alpha;
+    sc.eps_h2 = p->eps * p->h * p->h;
+    sc.cfl_ac = p->cfl_ac;
+    sc.cfl_f = p->cfl_f;
+    const double ka = wendland_alpha(p->dim, p->h);
+    sc.kW = ka;
+    sc.kF = -5.0 * ka / (p->h * p->h);
+    sc.W0 = ka;
+    for (int a = 0; a < 3; ++a) sc.g[a] = p->g[a];
+    sc.fh = (float)sc.h;
+    sc.finv_h = (float)sc.inv_h;
+    sc.fcs = (float)cs;
+    sc.fcut2 = (float)sc.cut2;
+    sc.fkW = (float)sc.kW;
+    sc.fkF = (float)sc.kF;
+    sc.feps_h2 = (float)sc.eps_h2;
+    for (int a = 0; a < 3; ++a) sc.fg[a] = (float)p->g[a];
+    build_layout(c);
+    *out = c;
+    g_err.clear();
+    return SPH_OK;
+}
+
+void sph_destroy(sph_ctx *ctx)
+{
+    if (!ctx) return;
+    drop_graphs(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (auto &r : ctx->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+sph_status sph_get_info(const sph_ctx *ctx, sph_info *info)
+{
+    if (!ctx || !info) return fail(SPH_E_ARG, "null argument");
+    info->n_fluid = ctx->N;
+    info->n_wall = ctx->Nw;
+    info->n_cells = ctx->C;
+    info->workspace_bytes = ctx->ws_bytes;
+    info->sigma0 = ctx->sc.sigma0;
+    info->mass = ctx->sc.mass;
+    info->cell_size = ctx->sc.cs;
+    info->steps_done = ctx->steps_done;
+    return SPH_OK;
+}
+
+sph_status sph_get_grid(const sph_ctx *ctx, int32_t b, double lo[3], int32_t ncell[3], int32_t *cell_base)
+{
+    if (!ctx || !lo || !ncell || !cell_base) return fail(SPH_E_ARG, "null argument");
+    if (b < 0 || b >= (int32_t)ctx->idev.size()) return fail(SPH_E_ARG, "instance out of range");
+    const InstDev &I = ctx->idev[b];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = I.lo[a];
+        ncell[a] = I.ncell[a];
+    }
+    *cell_base = I.cell_base;
+    return SPH_OK;
+}
+
+sph_status sph_workspace_size(const sph_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(SPH_E_ARG, "null argument");
+    *bytes = ctx->ws_bytes;
+    return SPH_OK;
+}
+
+sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
+{
+    if (!c || !b) return fail(SPH_E_ARG, "null argument");
+    hipStream_t s = as_stream(stream);
+    if (c->N > 0 && (!b->x || !b->v || !b->a || !b->rho || !b->id || !b->key || !b->perm || !b->count))
+        return fail(SPH_E_ARG, "missing fluid buffer");
+    if (c->Nw > 0 && (!b->xw || !b->wall_perm)) return fail(SPH_E_ARG, "missing wall buffer");
+    if (!b->cell_start || !b->wall_start || !b->dt || !b->diag || !b->workspace)
+        return fail(SPH_E_ARG, "missing table, per-instance or workspace buffer");
+    if (reinterpret_cast<uintptr_t>(b->workspace) % 256 != 0) return fail(SPH_E_ARG, "workspace must be 256-byte aligned");
+    drop_graphs(c);
+    c->buf = *b;
+    char *ws = static_cast<char *>(b->workspace);
+    Dev &d = c->dev;
+    d.x = b->x; d.v = b->v; d.a = b->a; d.rho = b->rho;
+    d.id = b->id; d.key = b->key; d.perm = b->perm; d.count = b->count;
+    d.xw = b->xw; d.wall_perm = b->wall_perm; d.cell_start = b->cell_start; d.wall_start = b->wall_start;
+    d.dt = b->dt; d.diag = b->diag;
+    d.skey = reinterpret_cast<int *>(ws + c->o_skey);
+    d.rk0 = reinterpret_cast<int *>(ws + c->o_rk0);
+    d.rv0 = reinterpret_cast<int *>(ws + c->o_rv0);
+    d.rk1 = reinterpret_cast<int *>(ws + c->o_rk1);
+    d.rv1 = reinterpret_cast<int *>(ws + c->o_rv1);
+    d.hist = reinterpret_cast<int *>(ws + c->o_hist);
+    d.part = reinterpret_cast<int *>(ws + c->o_part);
+    d.cnt = reinterpret_cast<int *>(ws + c->o_cnt);
+    d.pos = ws + c->o_pos;
+    d.vel = ws + c->o_vel;
+    d.rp = ws + c->o_rp;
+    d.scratch = reinterpret_cast<double *>(ws + c->o_rec);
+    d.wpos = ws + c->o_wpos;
+    d.wkey = reinterpret_cast<int *>(ws + c->o_wkey);
+    d.wskey = reinterpret_cast<int *>(ws + c->o_wskey);
+    d.partials = reinterpret_cast<double *>(ws + c->o_partials);
+    d.fmap = reinterpret_cast<Chunk *>(ws + c->o_fmap);
+    d.wmap = reinterpret_cast<Chunk *>(ws + c->o_wmap);
+    d.inst = reinterpret_cast<InstDev *>(ws + c->o_inst);
+    d.flags = reinterpret_cast<unsigned *>(ws + c->o_flags);
+    d.clampc = reinterpret_cast<int *>(ws + c->o_clampc);
+    d.nfchunks = (int)c->fmap.size();
+    d.nwchunks = (int)c->wmap.size();
+    d.block = c->block;
+    d.queue_cap = c->p.queue_cap;
+    if (!c->fmap.empty())
+        HIP_TRY(hipMemcpyAsync(d.fmap, c->fmap.data(), sizeof(Chunk) * c->fmap.size(), hipMemcpyHostToDevice, s));
+    if (!c->wmap.empty())
+        HIP_TRY(hipMemcpyAsync(d.wmap, c->wmap.data(), sizeof(Chunk) * c->wmap.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d.inst, c->idev.data(), sizeof(InstDev) * c->idev.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_i32(d.cnt, c->C + 1, 0, s));
+    HIP_TRY(launch_fill_i32(reinterpret_cast<int *>(d.flags), 16, 0, s));
+    HIP_TRY(launch_fill_i32(d.clampc, (int64_t)c->idev.size(), 0, s));
+    // static wall table
+    HIP_TRY(launch_wall_keys(c->sc, d, s));
+    HIP_TRY(launch_exclusive_scan(d.cnt, d.wall_start, c->C + 1, d.part, 1, s));
+    HIP_TRY(launch_radix_sort(d.wkey, c->Nw, c->C, d.wskey, d.wall_perm, d.rk0, d.rv0, d.rk1, d.rv1,
+                              d.hist, d.part, s));
+    HIP_TRY(launch_wall_pack(c->sc, d, c->mixed, s));
+    HIP_TRY(launch_fill_i32(d.clampc, (int64_t)c->idev.size(), 0, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    c->bound = true;
+    c->primed = false;
+    c->cells_built = false;
+    c->steps_done = 0;
+    return SPH_OK;
+}
+
+sph_status sph_prime(sph_ctx *c, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    hipStream_t s = as_stream(stream);
+    const Dev &d = c->dev;
+    HIP_TRY(launch_fill_f64(d.diag, (int64_t)c->idev.size() * SPH_NDIAG, 0.0, s));
+    HIP_TRY(launch_fill_i32(d.cnt, c->C + 1, 0, s));
+    TRY(do_keys(c, 0, s, false));
+    TRY(do_sort(c, false, s, false));
+    TRY(do_density(c, 0, s, false));
+    TRY(do_force(c, 0, s, false));
+    TRY(check_launch(launch_half2(c->sc, d, s, 0), "state partials"));
+    TRY(do_reduce(c, 1, s, false));
+    c->primed = true;
+    c->cells_built = false;
+    c->steps_done = 0;
+    return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx *c, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->cells_built) return fail(SPH_E_STATE, "cells already built: call sph_sort first");
+    TRY(do_keys(c, 0, as_stream(stream), c->timing));
+    c->cells_built = true;
+    return SPH_OK;
+}
+
+sph_status sph_sort(sph_ctx *c, int32_t reorder, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (!c->cells_built) return fail(SPH_E_STATE, "sph_build_cells (or sph_integrate half 1) first");
+    TRY(do_sort(c, reorder != 0, as_stream(stream), c->timing));
+    c->cells_built = false;
+    return SPH_OK;
+}
+
+sph_status sph_density(sph_ctx *c, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    return do_density(c, 1, as_stream(stream), c->timing);
+}
+
+sph_status sph_forces(sph_ctx *c, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    return do_force(c, 0, as_stream(stream), c->timing);
+}
+
+sph_status sph_integrate(sph_ctx *c, int32_t half, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (half != 1 && half != 2) return fail(SPH_E_ARG, "half must be 1 or 2");
+    hipStream_t s = as_stream(stream);
+    if (half == 1) {
+        if (c->cells_built) return fail(SPH_E_STATE, "cells already built: call sph_sort first");
+        TRY(do_keys(c, 1, s, c->timing));
+        c->cells_built = true;
+        return SPH_OK;
+    }
+    TRY(check_launch(launch_half2(c->sc, c->dev, s, 1), "half 2"));
+    TRY(do_reduce(c, 0, s, c->timing));
+    c->steps_done += 1;
+    return SPH_OK;
+}
+
+sph_status sph_step_batched(sph_ctx *c, int32_t n_steps, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    if (n_steps < 0) return fail(SPH_E_ARG, "n_steps must be >= 0");
+    if (!c->bound || !c->primed) return fail(SPH_E_STATE, "sph_bind and sph_prime first");
+    if (c->cells_built) return fail(SPH_E_STATE, "a staged step is half done");
+    hipStream_t s = as_stream(stream);
+    const bool graph = c->p.use_graph && !c->timing;
+    for (int32_t it = 0; it < n_steps; ++it) {
+        const bool ro = reorder_due(c);
+        if (graph) {
+            TRY(ensure_graph(c, ro ? 1 : 0));
+            HIP_TRY(hipGraphLaunch(c->gexec[ro ? 1 : 0], s));
+        } else {
+            TRY(enqueue_step(c, ro, s, c->timing));
+        }
+        c->steps_done += 1;
+    }
+    return SPH_OK;
+}
+
+sph_status sph_poll_errors(sph_ctx *c, uint32_t *flags, void *stream)
+{
+    if (!c || !flags) return fail(SPH_E_ARG, "null argument");
+    if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    hipStream_t s = as_stream(stream);
+    unsigned host = 0;
+    HIP_TRY(hipMemcpyAsync(&host, c->dev.flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(launch_fill_i32(reinterpret_cast<int *>(c->dev.flags), 1, 0, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *flags = host;
+    return SPH_OK;
+}
+
+sph_status sph_set_timing(sph_ctx *c, int32_t enable)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    c->timing = enable != 0;
+    return SPH_OK;
+}
+
+sph_status sph_stage_times(sph_ctx *c, double *ms, int64_t *launches, int32_t n, int32_t reset, void *stream)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+    collect_times(c);
+    for (int32_t i = 0; i < n && i < ST_COUNT; ++i) {
+        if (ms) ms[i] = c->stage_ms[i];
+        if (launches) launches[i] = c->stage_n[i];
+    }
+    if (reset) {
+        for (int i = 0; i < ST_COUNT; ++i) {
+            c->stage_ms[i] = 0.0;
+            c->stage_n[i] = 0;
+        }
+    }
+    return SPH_OK;
+}
+
+}  // extern "C"

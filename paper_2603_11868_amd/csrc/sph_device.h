@@ -1,0 +1,127 @@
+// Device-side types and helpers shared by the HIP kernels of libsph.
+//
+// Particle data on the GPU:
+//   storage order  the caller's FP64 state (x, v, a, rho, id) in
+//                  component-major SoA; it is physically reordered by cell
+//                  every K steps, so between reorders it stays nearly sorted;
+//   sorted order   per-step sweep records built right after the sort, one
+//                  aligned record per particle so that a candidate costs one
+//                  or two vector loads: position and velocity (FP64, or FP32
+//                  offsets from the FP64 origin of the particle's cell), and
+//                  the (rho, P) pair written by the density sweep.
+// Work is split into chunks of at most one block of consecutive particles of
+// one instance, so every block knows its instance and reductions never mix
+// instances.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sphx {
+
+constexpr int kMaxBlock = 256;
+constexpr int kNPart = 16;            // per-chunk partial sums (see k_final_reduce)
+
+struct __align__(16) dvec2 { double x, y; };
+struct __align__(32) dvec4 { double x, y, z, w; };
+struct __align__(8) fvec2 { float x, y; };
+struct __align__(16) fvec4 { float x, y, z, w; };
+
+struct Chunk {
+    int inst;                          // instance of the chunk
+    int begin;                         // first particle (global index)
+    int end;                           // one past the last
+    int pad;
+};
+
+struct InstDev {
+    double lo[3];                      // grid origin
+    int ncell[3];                      // cells per axis (1 on unused axes)
+    int cell_base;                     // first global cell of the instance
+    int fluid_off, n_fluid;
+    int wall_off, n_wall;
+    int chunk_begin, chunk_end;        // fluid chunks of the instance
+    double c0;
+};
+
+struct SimConst {
+    int dim, n_inst, N, Nw, C;
+    int pad0;
+    double h, inv_h, cs, inv_cs, cut2;
+    double rho0, mass, sigma0, alpha, eps_h2, cfl_ac, cfl_f;
+    double kW, kF, W0;                 // W = kW t^4 (2q+1), F = kF t^3, t = 1 - q/2
+    double g[3];
+    float fh, finv_h, fcs, fcut2, fkW, fkF, feps_h2, pad1;
+    float fg[3], pad2;
+};
+
+// Record types per (dimension, precision).
+template <int DIM, bool MIXED> struct Rec;
+template <> struct Rec<2, false> { using pos_t = dvec2; using vel_t = dvec2; using rp_t = dvec2; using real = double; };
+template <> struct Rec<3, false> { using pos_t = dvec4; using vel_t = dvec4; using rp_t = dvec2; using real = double; };
+template <> struct Rec<2, true>  { using pos_t = fvec2; using vel_t = fvec2; using rp_t = fvec2; using real = float; };
+template <> struct Rec<3, true>  { using pos_t = fvec4; using vel_t = fvec4; using rp_t = fvec2; using real = float; };
+
+// ---- wave64 primitives ------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` below this lane (v_mbcnt).
+__device__ __forceinline__ int mbcnt(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_scan(int v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan of one int per thread (blockDim.x <= 1024, multiple of
+// 64).  `lds` must hold blockDim.x/64 + 1 ints.  Returns the prefix; *total is
+// the block sum.  Contains barriers: every thread of the block must call it.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int *total)
+{
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    int inc = wave_inclusive_scan(v);
+    if (lane == 63) lds[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        int t = (lane < nw) ? lds[lane] : 0;
+        int ti = wave_inclusive_scan(t);
+        if (lane < nw) lds[lane] = ti - t;
+        if (lane == nw - 1) lds[nw] = ti;
+    }
+    __syncthreads();
+    int res = inc - v + lds[wid];
+    *total = lds[nw];
+    __syncthreads();
+    return res;
+}
+
+// Deterministic sum over a wave (fixed butterfly order).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+}  // namespace sphx

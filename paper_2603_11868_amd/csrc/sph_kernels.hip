@@ -1,0 +1,807 @@
+// Physics kernels of libsph: keys, reorder, sweep records, the density and
+// force sweeps (direct search over the 3^d nearest cells, Sec. 5 of the
+// paper), half-step integration and the FP64 reductions.
+//
+// Every per-particle kernel runs over a chunk map: block b handles particles
+// [map[b].begin, map[b].end) of instance map[b].inst, consecutive in storage
+// order (streaming kernels) or in sorted order (sweeps).  Sorted order keeps
+// the instances in the same ranges as storage order because the global cell
+// key is the instance's cell base plus its local key.
+#include "sph_launch.h"
+
+namespace sphx {
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_i32(int *p, int64_t n, int val)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double val)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+static int fill_grid(int64_t n)
+{
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<fill_grid(n), 256, 0, s>>>(p, n, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int64_t n, double val, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_f64<<<fill_grid(n), 256, 0, s>>>(p, n, val);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+
+// floor((x - lo) * inv_cs) clamped to [0, n); subtract then multiply, no FMA.
+__device__ __forceinline__ int cell_1d(double x, double lo, double inv_cs, int n, int &clamped)
+{
+#pragma clang fp contract(off)
+    const double t = floor((x - lo) * inv_cs);
+    if (!(t >= 0.0)) { clamped = 1; return 0; }
+    if (t >= (double)n) { clamped = 1; return n - 1; }
+    return (int)t;
+}
+
+// Half-step kick and drift, rounded like the plain expressions (no FMA).
+__device__ __forceinline__ void kick_drift(double &x, double &v, double a, double dt)
+{
+#pragma clang fp contract(off)
+    v = v + 0.5 * dt * a;
+    x = x + dt * v;
+}
+
+__device__ __forceinline__ double kick(double v, double a, double dt)
+{
+#pragma clang fp contract(off)
+    return v + 0.5 * dt * a;
+}
+
+// cnt[key] += 1 for every valid lane, one atomic per distinct key of the wave.
+__device__ __forceinline__ void aggregated_count(int *cnt, int key, bool valid)
+{
+    uint64_t rem = __ballot(valid);
+    while (rem) {
+        const int leader = __ffsll((unsigned long long)rem) - 1;
+        const int lk = __shfl(key, leader, 64);
+        const uint64_t m = __ballot(valid && key == lk);
+        if (lane_id() == leader) atomicAdd(&cnt[lk], (int)__popcll(m));
+        rem &= ~m;
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_keys(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    double *__restrict__ x, double *__restrict__ v, const double *__restrict__ a,
+    const double *__restrict__ dt, int kick_on, int n, int *__restrict__ key,
+    int *__restrict__ cnt, int *__restrict__ clampc, unsigned *__restrict__ flags)
+{
+    const Chunk ch = map[blockIdx.x];
+    const int i = ch.begin + threadIdx.x;
+    const bool act = i < ch.end;
+    int k = 0;
+    int clamped = 0;
+    if (act) {
+        const InstDev &I = inst[ch.inst];
+        double xi[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xi[c] = x[(int64_t)c * n + i];
+        if (kick_on) {
+            const double dtb = dt[ch.inst];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                double vc = v[(int64_t)c * n + i];
+                kick_drift(xi[c], vc, a[(int64_t)c * n + i], dtb);
+                v[(int64_t)c * n + i] = vc;
+                x[(int64_t)c * n + i] = xi[c];
+            }
+        }
+        int cc[3] = {0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) cc[c] = cell_1d(xi[c], I.lo[c], sc.inv_cs, I.ncell[c], clamped);
+        k = I.cell_base + cc[0] + I.ncell[0] * (cc[1] + I.ncell[1] * cc[2]);
+        key[i] = k;
+    }
+    aggregated_count(cnt, k, act);
+    const uint64_t cm = __ballot(act && clamped);
+    if (cm && lane_id() == 0) {
+        atomicAdd(&clampc[ch.inst], (int)__popcll(cm));
+        atomicOr(flags, 1u);
+    }
+}
+
+hipError_t launch_keys(const SimConst &sc, const Dev &d, int kick_on, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2)
+        k_keys<2><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.inst, d.x, d.v, d.a, d.dt, kick_on,
+                                                  sc.N, d.key, d.cnt, d.clampc, d.flags);
+    else
+        k_keys<3><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.inst, d.x, d.v, d.a, d.dt, kick_on,
+                                                  sc.N, d.key, d.cnt, d.clampc, d.flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_keys(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    if (d.nwchunks <= 0) return hipSuccess;
+    // walls are read only: kick is off, so x and v are never written
+    double *xw = const_cast<double *>(d.xw);
+    if (sc.dim == 2)
+        k_keys<2><<<d.nwchunks, d.block, 0, s>>>(sc, d.wmap, d.inst, xw, nullptr, nullptr, d.dt, 0,
+                                                  sc.Nw, d.wkey, d.cnt, d.clampc, d.flags);
+    else
+        k_keys<3><<<d.nwchunks, d.block, 0, s>>>(sc, d.wmap, d.inst, xw, nullptr, nullptr, d.dt, 0,
+                                                  sc.Nw, d.wkey, d.cnt, d.clampc, d.flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reorder and sweep records
+// ---------------------------------------------------------------------------
+
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_reorder_gather(
+    const Chunk *__restrict__ map, const int *__restrict__ perm, const double *__restrict__ x,
+    const double *__restrict__ v, const double *__restrict__ rho, const int *__restrict__ id,
+    double *__restrict__ scr, int n)
+{
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const int i = perm[k];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        scr[(int64_t)c * n + k] = x[(int64_t)c * n + i];
+        scr[(int64_t)(DIM + c) * n + k] = v[(int64_t)c * n + i];
+    }
+    scr[(int64_t)(2 * DIM) * n + k] = rho[i];
+    reinterpret_cast<int *>(scr + (int64_t)(2 * DIM + 1) * n)[k] = id[i];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_reorder_copy(
+    const Chunk *__restrict__ map, const double *__restrict__ scr, const int *__restrict__ skey,
+    double *__restrict__ x, double *__restrict__ v, double *__restrict__ rho,
+    int *__restrict__ id, int *__restrict__ perm, int *__restrict__ key, int n)
+{
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        x[(int64_t)c * n + k] = scr[(int64_t)c * n + k];
+        v[(int64_t)c * n + k] = scr[(int64_t)(DIM + c) * n + k];
+    }
+    rho[k] = scr[(int64_t)(2 * DIM) * n + k];
+    id[k] = reinterpret_cast<const int *>(scr + (int64_t)(2 * DIM + 1) * n)[k];
+    perm[k] = k;
+    key[k] = skey[k];
+}
+
+hipError_t launch_reorder(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) {
+        k_reorder_gather<2><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.perm, d.x, d.v, d.rho, d.id, d.scratch, sc.N);
+        k_reorder_copy<2><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.scratch, d.skey, d.x, d.v, d.rho, d.id, d.perm, d.key, sc.N);
+    } else {
+        k_reorder_gather<3><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.perm, d.x, d.v, d.rho, d.id, d.scratch, sc.N);
+        k_reorder_copy<3><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.scratch, d.skey, d.x, d.v, d.rho, d.id, d.perm, d.key, sc.N);
+    }
+    return hipGetLastError();
+}
+
+template <int DIM, bool MIXED>
+__device__ __forceinline__ typename Rec<DIM, MIXED>::pos_t make_pos(const double *xi, const InstDev &I,
+                                                                    int local_key, double cs)
+{
+    typename Rec<DIM, MIXED>::pos_t p;
+    if constexpr (MIXED) {
+        const int cx = local_key % I.ncell[0];
+        const int t = local_key / I.ncell[0];
+        const int cy = t % I.ncell[1];
+        const int cz = t / I.ncell[1];
+        p.x = (float)(xi[0] - (I.lo[0] + cx * cs));
+        p.y = (float)(xi[1] - (I.lo[1] + cy * cs));
+        if constexpr (DIM == 3) {
+            p.z = (float)(xi[2] - (I.lo[2] + cz * cs));
+            p.w = 0.0f;
+        }
+        (void)cz;
+    } else {
+        p.x = xi[0];
+        p.y = xi[1];
+        if constexpr (DIM == 3) {
+            p.z = xi[2];
+            p.w = 0.0;
+        }
+    }
+    return p;
+}
+
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(kMaxBlock) void k_pack(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const double *__restrict__ x, const double *__restrict__ v, const int *__restrict__ perm,
+    const int *__restrict__ skey, int n, typename Rec<DIM, MIXED>::pos_t *__restrict__ pos,
+    typename Rec<DIM, MIXED>::vel_t *__restrict__ vel)
+{
+    using R = Rec<DIM, MIXED>;
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const InstDev &I = inst[ch.inst];
+    const int i = perm[k];
+    double xi[DIM];
+    typename R::vel_t vv;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) xi[c] = x[(int64_t)c * n + i];
+    vv.x = (typename R::real)v[i];
+    vv.y = (typename R::real)v[(int64_t)n + i];
+    if constexpr (DIM == 3) {
+        vv.z = (typename R::real)v[(int64_t)2 * n + i];
+        vv.w = 0;
+    }
+    pos[k] = make_pos<DIM, MIXED>(xi, I, skey[k] - I.cell_base, sc.cs);
+    vel[k] = vv;
+}
+
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(kMaxBlock) void k_wall_pack(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const double *__restrict__ xw, const int *__restrict__ wperm, const int *__restrict__ wskey,
+    int nw, typename Rec<DIM, MIXED>::pos_t *__restrict__ wpos)
+{
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const InstDev &I = inst[ch.inst];
+    const int j = wperm[k];
+    double xj[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) xj[c] = xw[(int64_t)c * nw + j];
+    wpos[k] = make_pos<DIM, MIXED>(xj, I, wskey[k] - I.cell_base, sc.cs);
+}
+
+template <int DIM, bool MIXED>
+static void pack_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    using R = Rec<DIM, MIXED>;
+    k_pack<DIM, MIXED><<<d.nfchunks, d.block, 0, s>>>(
+        sc, d.fmap, d.inst, d.x, d.v, d.perm, d.skey, sc.N,
+        static_cast<typename R::pos_t *>(d.pos), static_cast<typename R::vel_t *>(d.vel));
+}
+
+hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) pack_dispatch<2, true>(sc, d, s); else pack_dispatch<2, false>(sc, d, s); }
+    else { if (mixed) pack_dispatch<3, true>(sc, d, s); else pack_dispatch<3, false>(sc, d, s); }
+    return hipGetLastError();
+}
+
+template <int DIM, bool MIXED>
+static void wall_pack_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    using R = Rec<DIM, MIXED>;
+    k_wall_pack<DIM, MIXED><<<d.nwchunks, d.block, 0, s>>>(
+        sc, d.wmap, d.inst, d.xw, d.wall_perm, d.wskey, sc.Nw,
+        static_cast<typename R::pos_t *>(d.wpos));
+}
+
+hipError_t launch_wall_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
+{
+    if (d.nwchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) wall_pack_dispatch<2, true>(sc, d, s); else wall_pack_dispatch<2, false>(sc, d, s); }
+    else { if (mixed) wall_pack_dispatch<3, true>(sc, d, s); else wall_pack_dispatch<3, false>(sc, d, s); }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// neighbour traversal
+// ---------------------------------------------------------------------------
+
+// r^2 summed left to right without FMA: the predicate r^2 < (2h)^2 of the FP64
+// path then matches a plain IEEE evaluation bit for bit.
+__device__ __forceinline__ double dist2(double rx, double ry)
+{
+#pragma clang fp contract(off)
+    return rx * rx + ry * ry;
+}
+__device__ __forceinline__ double dist2(double rx, double ry, double rz)
+{
+#pragma clang fp contract(off)
+    return rx * rx + ry * ry + rz * rz;
+}
+__device__ __forceinline__ float dist2(float rx, float ry) { return rx * rx + ry * ry; }
+__device__ __forceinline__ float dist2(float rx, float ry, float rz) { return rx * rx + ry * ry + rz * rz; }
+
+// Calls fn(wall, s, r[], r2) for every neighbour of sorted target k (fluid
+// slots of a stencil row first, then its wall slots; rows in z, y order).
+// In the mixed path the pair vector is rebuilt from the FP32 offsets and the
+// exact cell distance: r = (o_i - o_j) - (c_j - c_i) cs.
+template <int DIM, bool MIXED, class Fn>
+__device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev &I, int lk, int k,
+                                               const typename Rec<DIM, MIXED>::pos_t &pi,
+                                               const int *__restrict__ cstart,
+                                               const int *__restrict__ wstart,
+                                               const typename Rec<DIM, MIXED>::pos_t *__restrict__ pos,
+                                               const typename Rec<DIM, MIXED>::pos_t *__restrict__ wpos,
+                                               Fn &&fn)
+{
+    using real = typename Rec<DIM, MIXED>::real;
+    const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
+    const int cx = lk % ncx;
+    const int tq = lk / ncx;
+    const int cy = tq % ncy;
+    const int cz = tq / ncy;
+    const int xlo = cx > 0 ? cx - 1 : 0;
+    const int xhi = cx < ncx - 1 ? cx + 1 : ncx - 1;
+    const int dz_lo = (DIM == 3 && cz > 0) ? -1 : 0;
+    const int dz_hi = (DIM == 3 && cz < ncz - 1) ? 1 : 0;
+    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
+    for (int dz = dz_lo; dz <= dz_hi; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = cy + dy;
+            if (yy < 0 || yy >= ncy) continue;
+            const int row = I.cell_base + (yy + ncy * (cz + dz)) * ncx;
+            real tx0 = 0, ty = 0, tz = 0;
+            if constexpr (MIXED) {
+                tx0 = pi.x - (real)(xlo - cx) * cs;
+                ty = pi.y - (real)dy * cs;
+                if constexpr (DIM == 3) tz = pi.z - (real)dz * cs;
+            }
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int *__restrict__ st = pass == 0 ? cstart : wstart;
+                const typename Rec<DIM, MIXED>::pos_t *__restrict__ src = pass == 0 ? pos : wpos;
+                const int s0 = st[row + xlo];
+                const int s1 = st[row + xhi + 1];
+                int b1 = s1, b2 = s1;
+                if constexpr (MIXED) {
+                    if (xlo + 1 <= xhi) b1 = st[row + xlo + 1];
+                    if (xlo + 2 <= xhi) b2 = st[row + xlo + 2];
+                }
+                for (int s = s0; s < s1; ++s) {
+                    if (pass == 0 && s == k) continue;
+                    const auto pj = src[s];
+                    real r[3];
+                    if constexpr (MIXED) {
+                        const real tx = s < b1 ? tx0 : (s < b2 ? tx0 - cs : tx0 - 2 * cs);
+                        r[0] = tx - pj.x;
+                        r[1] = ty - pj.y;
+                        if constexpr (DIM == 3) r[2] = tz - pj.z;
+                    } else {
+                        r[0] = pi.x - pj.x;
+                        r[1] = pi.y - pj.y;
+                        if constexpr (DIM == 3) r[2] = pi.z - pj.z;
+                    }
+                    real r2;
+                    if constexpr (DIM == 3) r2 = dist2(r[0], r[1], r[2]);
+                    else r2 = dist2(r[0], r[1]);
+                    if (r2 < (MIXED ? (real)sc.fcut2 : (real)sc.cut2)) fn(pass == 1, s, r, r2);
+                }
+            }
+        }
+    }
+}
+
+template <class real>
+__device__ __forceinline__ void kernel_WF(real r2, real inv_h, real kW, real kF, real &W, real &F)
+{
+    const real rr = sqrt(r2);
+    const real q = rr * inv_h;
+    const real t = (real)1 - (real)0.5 * q;
+    const real t3 = t * t * t;
+    W = kW * t3 * t * ((real)2 * q + (real)1);
+    F = kF * t3;
+}
+
+template <class real>
+__device__ __forceinline__ void kernel_F(real r2, real inv_h, real kF, real &F)
+{
+    const real rr = sqrt(r2);
+    const real q = rr * inv_h;
+    const real t = (real)1 - (real)0.5 * q;
+    F = kF * t * t * t;
+}
+
+// ---------------------------------------------------------------------------
+// density sweep
+// ---------------------------------------------------------------------------
+
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(kMaxBlock) void k_density(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
+    const int *__restrict__ wstart, const typename Rec<DIM, MIXED>::pos_t *__restrict__ pos,
+    const typename Rec<DIM, MIXED>::vel_t *__restrict__ vel,
+    const typename Rec<DIM, MIXED>::pos_t *__restrict__ wpos, double *__restrict__ rho,
+    int *__restrict__ count, typename Rec<DIM, MIXED>::rp_t *__restrict__ rp,
+    const double *__restrict__ dt, int use_dt)
+{
+    using R = Rec<DIM, MIXED>;
+    using real = typename R::real;
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const InstDev &I = inst[ch.inst];
+    const int lk = skey[k] - I.cell_base;
+    const typename R::pos_t pi = pos[k];
+    const typename R::vel_t vi = vel[k];
+    const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
+    const real kW = MIXED ? (real)sc.fkW : (real)sc.kW;
+    const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
+    real sigma = MIXED ? (real)0 : (real)sc.W0;
+    real drho = 0;
+    int cnt = 0;
+    for_neighbours<DIM, MIXED>(sc, I, lk, k, pi, cstart, wstart, pos, wpos,
+        [&](bool wall, int s, const real *r, real r2) {
+            real W, F;
+            kernel_WF(r2, inv_h, kW, kF, W, F);
+            real vr;
+            if (wall) {
+                vr = vi.x * r[0] + vi.y * r[1];
+                if constexpr (DIM == 3) vr += vi.z * r[2];
+            } else {
+                const typename R::vel_t vj = vel[s];
+                vr = (vi.x - vj.x) * r[0] + (vi.y - vj.y) * r[1];
+                if constexpr (DIM == 3) vr += (vi.z - vj.z) * r[2];
+            }
+            sigma += W;
+            drho += vr * F;
+            ++cnt;
+        });
+    const int i = perm[k];
+    const double sig = MIXED ? sc.W0 + (double)sigma : (double)sigma;
+    const double rho_sum = sc.mass * sig;
+    const double dtb = use_dt ? dt[ch.inst] : 0.0;
+    const double rho_star = rho[i] + dtb * (sc.mass * (double)drho);
+    const double excess = rho_star - rho_sum;
+    const double rn = excess > 0.0 ? rho_sum + excess * sc.rho0 / rho_star : rho_sum;
+    double p = I.c0 * I.c0 * (rn - sc.rho0);
+    if (p < 0.0) p = 0.0;
+    const double P = p / (rn * rn);
+    rho[i] = rn;
+    count[i] = cnt;
+    typename R::rp_t out;
+    out.x = (real)rn;
+    out.y = (real)P;
+    rp[k] = out;
+}
+
+template <int DIM, bool MIXED>
+static void density_dispatch(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
+{
+    using R = Rec<DIM, MIXED>;
+    k_density<DIM, MIXED><<<d.nfchunks, d.block, 0, s>>>(
+        sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start,
+        static_cast<const typename R::pos_t *>(d.pos), static_cast<const typename R::vel_t *>(d.vel),
+        static_cast<const typename R::pos_t *>(d.wpos), d.rho, d.count,
+        static_cast<typename R::rp_t *>(d.rp), d.dt, use_dt);
+}
+
+hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) density_dispatch<2, true>(sc, d, use_dt, s); else density_dispatch<2, false>(sc, d, use_dt, s); }
+    else { if (mixed) density_dispatch<3, true>(sc, d, use_dt, s); else density_dispatch<3, false>(sc, d, use_dt, s); }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// block partial sums (deterministic: fixed lanes, fixed butterfly, fixed wave order)
+// ---------------------------------------------------------------------------
+
+// slots: 0 max|v| 1 max|a| 2..4 sum m v 5 kinetic 6 potential 7 internal
+//        8..10 sum m a_ff 11 sum rho 12 pairs 13 non-finite count
+enum { P_VMAX = 0, P_AMAX = 1, P_MOM = 2, P_KE = 5, P_PE = 6, P_IE = 7, P_FF = 8,
+       P_RHO = 11, P_PAIRS = 12, P_BAD = 13 };
+
+__device__ __forceinline__ bool is_max_slot(int s) { return s == P_VMAX || s == P_AMAX; }
+
+// Reduce vals[lo..hi) over the block and write them to out[lo..hi).
+template <int LO, int HI>
+__device__ __forceinline__ void block_partials(double (&vals)[kNPart], double *__restrict__ out)
+{
+    __shared__ double sh[kMaxBlock / 64][kNPart];
+    const int w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int s = LO; s < HI; ++s) {
+        const double r = is_max_slot(s) ? wave_max(vals[s]) : wave_sum(vals[s]);
+        if (lane_id() == 0) sh[w][s] = r;
+    }
+    __syncthreads();
+    const int s = threadIdx.x + LO;
+    if (s < HI) {
+        double r = sh[0][s];
+        for (int q = 1; q < nw; ++q) r = is_max_slot(s) ? fmax(r, sh[q][s]) : r + sh[q][s];
+        out[s] = r;
+    }
+}
+
+// Contributions of one particle to the step diagnostics (FP64).
+template <int DIM>
+__device__ __forceinline__ void state_partials(const SimConst &sc, const InstDev &I, const double *vn,
+                                               const double *an, const double *xi, double rhoi,
+                                               double (&vals)[kNPart])
+{
+    double v2 = 0, a2 = 0, gx = 0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        v2 += vn[c] * vn[c];
+        a2 += an[c] * an[c];
+        gx += sc.g[c] * xi[c];
+        vals[P_MOM + c] = sc.mass * vn[c];
+    }
+    const double vm = sqrt(v2), am = sqrt(a2);
+    vals[P_VMAX] = vm;
+    vals[P_AMAX] = am;
+    vals[P_KE] = 0.5 * sc.mass * v2;
+    vals[P_PE] = -sc.mass * gx;
+    vals[P_IE] = rhoi > sc.rho0
+                     ? sc.mass * I.c0 * I.c0 * (log(rhoi / sc.rho0) + sc.rho0 / rhoi - 1.0)
+                     : 0.0;
+    vals[P_RHO] = rhoi;
+    vals[P_BAD] = (isfinite(vm) && isfinite(am)) ? 0.0 : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// force sweep (+ half 2 and partials when fused)
+// ---------------------------------------------------------------------------
+
+template <int DIM, bool MIXED, bool FUSED>
+__global__ __launch_bounds__(kMaxBlock) void k_force(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
+    const int *__restrict__ wstart, const typename Rec<DIM, MIXED>::pos_t *__restrict__ pos,
+    const typename Rec<DIM, MIXED>::vel_t *__restrict__ vel,
+    const typename Rec<DIM, MIXED>::pos_t *__restrict__ wpos,
+    const typename Rec<DIM, MIXED>::rp_t *__restrict__ rp, double *__restrict__ a,
+    double *__restrict__ v, const double *__restrict__ x, const double *__restrict__ rho,
+    const double *__restrict__ dt, double *__restrict__ partials, int n)
+{
+    using R = Rec<DIM, MIXED>;
+    using real = typename R::real;
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    const bool act = k < ch.end;
+    const InstDev &I = inst[ch.inst];
+    double vals[kNPart];
+#pragma unroll
+    for (int q = 0; q < kNPart; ++q) vals[q] = 0.0;
+    if (act) {
+        const int lk = skey[k] - I.cell_base;
+        const typename R::pos_t pi = pos[k];
+        const typename R::vel_t vi = vel[k];
+        const typename R::rp_t rpi = rp[k];
+        const real rho_i = rpi.x, P_i = rpi.y;
+        const real p_i = P_i * rho_i * rho_i;
+        const real inv_rho_i2 = (real)1 / (rho_i * rho_i);
+        const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
+        const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
+        const real visc_a = (real)(sc.alpha * I.c0 * sc.h);
+        const real eps_h2 = MIXED ? (real)sc.feps_h2 : (real)sc.eps_h2;
+        const real gx = MIXED ? (real)sc.fg[0] : (real)sc.g[0];
+        const real gy = MIXED ? (real)sc.fg[1] : (real)sc.g[1];
+        const real gz = MIXED ? (real)sc.fg[2] : (real)sc.g[2];
+        real acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
+        int cnt = 0;
+        for_neighbours<DIM, MIXED>(sc, I, lk, k, pi, cstart, wstart, pos, wpos,
+            [&](bool wall, int s, const real *r, real r2) {
+                real F;
+                kernel_F(r2, inv_h, kF, F);
+                real P_j, rho_j, vr;
+                if (wall) {
+                    real gr = gx * r[0] + gy * r[1];
+                    if constexpr (DIM == 3) gr += gz * r[2];
+                    real p_j = p_i - rho_i * gr;       // p_i + rho_i g.(x_j - x_i)
+                    if (p_j < (real)0) p_j = (real)0;
+                    P_j = p_j * inv_rho_i2;
+                    rho_j = rho_i;
+                    vr = vi.x * r[0] + vi.y * r[1];
+                    if constexpr (DIM == 3) vr += vi.z * r[2];
+                } else {
+                    const typename R::rp_t rpj = rp[s];
+                    const typename R::vel_t vj = vel[s];
+                    rho_j = rpj.x;
+                    P_j = rpj.y;
+                    vr = (vi.x - vj.x) * r[0] + (vi.y - vj.y) * r[1];
+                    if constexpr (DIM == 3) vr += (vi.z - vj.z) * r[2];
+                }
+                real visc = 0;
+                if (vr < (real)0)
+                    visc = -visc_a * vr / ((real)0.5 * (rho_i + rho_j) * (r2 + eps_h2));
+                const real coef = (P_i + P_j + visc) * F;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) acc[c] -= coef * r[c];
+                if (!wall) {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) aff[c] -= coef * r[c];
+                }
+                ++cnt;
+            });
+        const int i = perm[k];
+        double an[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            an[c] = sc.g[c] + sc.mass * (double)acc[c];
+            a[(int64_t)c * n + i] = an[c];
+            vals[P_FF + c] = sc.mass * (sc.mass * (double)aff[c]);
+        }
+        vals[P_PAIRS] = (double)cnt;
+        if constexpr (FUSED) {
+            const double dtb = dt[ch.inst];
+            double vn[DIM], xi[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                vn[c] = kick(v[(int64_t)c * n + i], an[c], dtb);
+                v[(int64_t)c * n + i] = vn[c];
+                xi[c] = x[(int64_t)c * n + i];
+            }
+            state_partials<DIM>(sc, I, vn, an, xi, rho[i], vals);
+        }
+    }
+    double *out = partials + (int64_t)blockIdx.x * kNPart;
+    if constexpr (FUSED) block_partials<0, P_BAD + 1>(vals, out);
+    else block_partials<P_FF, P_PAIRS + 1>(vals, out);
+}
+
+template <int DIM, bool MIXED, bool FUSED>
+static void force_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    using R = Rec<DIM, MIXED>;
+    k_force<DIM, MIXED, FUSED><<<d.nfchunks, d.block, 0, s>>>(
+        sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start,
+        static_cast<const typename R::pos_t *>(d.pos), static_cast<const typename R::vel_t *>(d.vel),
+        static_cast<const typename R::pos_t *>(d.wpos), static_cast<const typename R::rp_t *>(d.rp),
+        d.a, d.v, d.x, d.rho, d.dt, d.partials, sc.N);
+}
+
+hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) {
+        if (mixed) { if (fused) force_dispatch<2, true, true>(sc, d, s); else force_dispatch<2, true, false>(sc, d, s); }
+        else { if (fused) force_dispatch<2, false, true>(sc, d, s); else force_dispatch<2, false, false>(sc, d, s); }
+    } else {
+        if (mixed) { if (fused) force_dispatch<3, true, true>(sc, d, s); else force_dispatch<3, true, false>(sc, d, s); }
+        else { if (fused) force_dispatch<3, false, true>(sc, d, s); else force_dispatch<3, false, false>(sc, d, s); }
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// staged half 2
+// ---------------------------------------------------------------------------
+
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_half2(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    double *__restrict__ v, const double *__restrict__ a, const double *__restrict__ x,
+    const double *__restrict__ rho, const double *__restrict__ dt, double *__restrict__ partials,
+    int n, int kick_on)
+{
+    const Chunk ch = map[blockIdx.x];
+    const int i = ch.begin + threadIdx.x;
+    double vals[kNPart];
+#pragma unroll
+    for (int q = 0; q < kNPart; ++q) vals[q] = 0.0;
+    if (i < ch.end) {
+        const InstDev &I = inst[ch.inst];
+        const double dtb = kick_on ? dt[ch.inst] : 0.0;
+        double vn[DIM], an[DIM], xi[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            an[c] = a[(int64_t)c * n + i];
+            vn[c] = v[(int64_t)c * n + i];
+            if (kick_on) {
+                vn[c] = kick(vn[c], an[c], dtb);
+                v[(int64_t)c * n + i] = vn[c];
+            }
+            xi[c] = x[(int64_t)c * n + i];
+        }
+        state_partials<DIM>(sc, I, vn, an, xi, rho[i], vals);
+    }
+    double *out = partials + (int64_t)blockIdx.x * kNPart;
+    block_partials<0, P_FF>(vals, out);
+    // slots after the force sweep's share
+    block_partials<P_RHO, P_RHO + 1>(vals, out);
+    block_partials<P_BAD, P_BAD + 1>(vals, out);
+}
+
+hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kick_on)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2)
+        k_half2<2><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.inst, d.v, d.a, d.x, d.rho, d.dt, d.partials, sc.N, kick_on);
+    else
+        k_half2<3><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.inst, d.v, d.a, d.x, d.rho, d.dt, d.partials, sc.N, kick_on);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-instance reductions -> dt, diag
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_final_reduce(SimConst sc, const InstDev *__restrict__ inst,
+                                                      const double *__restrict__ partials,
+                                                      double *__restrict__ dt,
+                                                      double *__restrict__ diag,
+                                                      int *__restrict__ clampc,
+                                                      unsigned *__restrict__ flags, int prime)
+{
+    const int b = blockIdx.x;
+    const InstDev &I = inst[b];
+    double acc[kNPart];
+#pragma unroll
+    for (int q = 0; q < kNPart; ++q) acc[q] = 0.0;
+    for (int c = I.chunk_begin + threadIdx.x; c < I.chunk_end; c += blockDim.x) {
+        const double *p = partials + (int64_t)c * kNPart;
+#pragma unroll
+        for (int q = 0; q < kNPart; ++q) acc[q] = is_max_slot(q) ? fmax(acc[q], p[q]) : acc[q] + p[q];
+    }
+    __shared__ double tot[kNPart];
+    block_partials<0, kNPart>(acc, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *d = diag + (int64_t)b * 16;
+        const double dt_used = prime ? 0.0 : dt[b];
+        const double vmax = tot[P_VMAX], amax = tot[P_AMAX];
+        d[0] = vmax;
+        d[1] = amax;
+        d[2] = sc.mass * (double)I.n_fluid;
+        for (int c = 0; c < 3; ++c) d[3 + c] = tot[P_MOM + c];
+        d[6] = tot[P_KE];
+        d[7] = tot[P_PE];
+        d[8] = tot[P_IE];
+        const double ff = sqrt(tot[P_FF] * tot[P_FF] + tot[P_FF + 1] * tot[P_FF + 1] +
+                               tot[P_FF + 2] * tot[P_FF + 2]);
+        d[9] = ff;
+        d[10] = I.n_fluid > 0 ? tot[P_RHO] / ((double)I.n_fluid * sc.rho0) - 1.0 : 0.0;
+        d[11] += (double)clampc[b];
+        clampc[b] = 0;
+        d[12] = tot[P_PAIRS];
+        d[13] += dt_used * ff;
+        d[14] += dt_used;
+        d[15] = prime ? 0.0 : d[15] + 1.0;
+        const double dt_ac = sc.cfl_ac * sc.h / (I.c0 + vmax);
+        const double dt_f = sc.cfl_f * sqrt(sc.h / amax);
+        dt[b] = dt_ac < dt_f ? dt_ac : dt_f;
+        if (tot[P_BAD] > 0.0) atomicOr(flags, 2u);
+    }
+}
+
+hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s)
+{
+    if (sc.n_inst <= 0) return hipSuccess;
+    k_final_reduce<<<sc.n_inst, 256, 0, s>>>(sc, d.inst, d.partials, d.dt, d.diag, d.clampc, d.flags, prime);
+    return hipGetLastError();
+}
+
+}  // namespace sphx

@@ -1,0 +1,67 @@
+// Host-side launchers of the libsph kernels (internal to the library).
+#pragma once
+
+#include "sph_device.h"
+
+namespace sphx {
+
+// ---- scan and sort (sph_sort.hip) ---------------------------------------
+int scan_tiles(int64_t n);
+int64_t scan_max_elems();
+int radix_tiles(int64_t n);
+int radix_passes(int64_t ncells);
+hipError_t launch_exclusive_scan(int *in, int *out, int64_t n, int *part, int zero_in,
+                                 hipStream_t s);
+hipError_t launch_radix_sort(const int *keys, int64_t n, int64_t ncells, int *skey, int *perm,
+                             int *k0, int *v0, int *k1, int *v1, int *hist, int *part,
+                             hipStream_t s);
+
+// ---- physics (sph_kernels.hip) ------------------------------------------
+struct Dev {
+    // caller buffers
+    double *x, *v, *a, *rho;
+    int *id, *key, *perm, *count;
+    const double *xw;
+    int *wall_perm, *cell_start, *wall_start;
+    double *dt, *diag;
+    // workspace
+    int *skey, *rk0, *rv0, *rk1, *rv1, *hist, *part;
+    int *cnt;                 // [C+1] per-cell counts (zero between steps)
+    void *pos, *vel, *rp;     // sorted sweep records
+    void *wpos;               // sorted wall records
+    int *wkey, *wskey;        // wall keys (storage, sorted)
+    double *scratch;          // reorder gather buffer
+    double *partials;         // [nchunks * kNPart]
+    Chunk *fmap, *wmap;
+    InstDev *inst;
+    unsigned *flags;
+    int *clampc;              // [B] clamped keys of the current step
+    int nfchunks, nwchunks;
+    int block;                // threads per chunk
+    int queue_cap;
+};
+
+hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t n, double val, hipStream_t s);
+
+// Keys (optionally after the half-1 kick and drift) and per-cell counts.
+hipError_t launch_keys(const SimConst &sc, const Dev &d, int kick, hipStream_t s);
+// Wall keys and counts (bind time).
+hipError_t launch_wall_keys(const SimConst &sc, const Dev &d, hipStream_t s);
+// Sorted wall records (bind time).
+hipError_t launch_wall_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s);
+// Gather x, v, rho, id into sorted order; perm <- identity; key <- sorted keys.
+hipError_t launch_reorder(const SimConst &sc, const Dev &d, hipStream_t s);
+// Sorted sweep records from the storage-order state.
+hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s);
+// Density sweep.  use_dt = 0 for the prime (dt = 0).
+hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s);
+// Force sweep.  fused != 0: also v += dt/2 a and all per-chunk partials.
+hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, hipStream_t s);
+// Staged half 2: v += dt/2 a (kick_on != 0) and the partials the force sweep
+// does not write.
+hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kick_on);
+// Per-instance reductions of the partials -> dt, diag, flags.
+hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s);
+
+}  // namespace sphx

@@ -1,0 +1,224 @@
+// Device-wide exclusive scan and the stable LSD radix sort of cell keys.
+//
+// Radix sort (Sec. 5 of the paper sorts particles by cell with a radix sort):
+// 8-bit digits, least significant first, ceil(bits(C-1)/8) passes.  Each pass
+// is reduce-then-scan: per-tile digit histograms, one exclusive scan of the
+// digit-major histogram table, then a scatter in which every tile ranks its
+// keys stably.  Ranking inside a wave uses 8 ballots to find the lanes that
+// share a digit and v_mbcnt for the rank among them; across the 4 waves of a
+// block and the 16 rounds of a tile, per-digit counters in LDS keep the order
+// of the input.  Ties therefore keep their input order, and the result is the
+// unique stable permutation: identical to a plain counting sort of the keys.
+#include "sph_launch.h"
+
+namespace sphx {
+
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_IPT = 8;
+constexpr int SCAN_TILE = SCAN_BS * SCAN_IPT;
+constexpr int SCAN_TOP_BS = 1024;
+constexpr int SCAN_TOP_IPT = 16;
+
+constexpr int RS_BS = 256;
+constexpr int RS_IPT = 16;
+constexpr int RS_TILE = RS_BS * RS_IPT;
+constexpr int RS_RADIX = 256;
+
+int scan_tiles(int64_t n) { return (int)((n + SCAN_TILE - 1) / SCAN_TILE); }
+int64_t scan_max_elems() { return (int64_t)SCAN_TOP_BS * SCAN_TOP_IPT * SCAN_TILE; }
+int radix_tiles(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
+
+__global__ __launch_bounds__(SCAN_BS) void k_scan_reduce(const int *__restrict__ in, int n,
+                                                         int *__restrict__ part)
+{
+    __shared__ int lds[SCAN_BS / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t idx = base + j;
+        if (idx < n) s += in[idx];
+    }
+    int tot;
+    block_exclusive_scan(s, lds, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_TOP_BS) void k_scan_top(int *__restrict__ part, int ntiles)
+{
+    __shared__ int lds[SCAN_TOP_BS / 64 + 1];
+    const int base = threadIdx.x * SCAN_TOP_IPT;
+    int v[SCAN_TOP_IPT];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_TOP_IPT; ++j) {
+        int idx = base + j;
+        v[j] = (idx < ntiles) ? part[idx] : 0;
+        s += v[j];
+    }
+    int tot;
+    int off = block_exclusive_scan(s, lds, &tot);
+#pragma unroll
+    for (int j = 0; j < SCAN_TOP_IPT; ++j) {
+        int idx = base + j;
+        if (idx < ntiles) part[idx] = off;
+        off += v[j];
+    }
+}
+
+__global__ __launch_bounds__(SCAN_BS) void k_scan_apply(int *__restrict__ in, int *__restrict__ out,
+                                                        int n, const int *__restrict__ part,
+                                                        int zero_in)
+{
+    __shared__ int lds[SCAN_BS / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int v[SCAN_IPT];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t idx = base + j;
+        v[j] = (idx < n) ? in[idx] : 0;
+        s += v[j];
+    }
+    int tot;
+    int off = block_exclusive_scan(s, lds, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t idx = base + j;
+        if (idx < n) {
+            out[idx] = off;
+            if (zero_in) in[idx] = 0;
+        }
+        off += v[j];
+    }
+}
+
+// Exclusive scan of n ints (out may alias in).  part: scan_tiles(n) ints.
+hipError_t launch_exclusive_scan(int *in, int *out, int64_t n, int *part, int zero_in,
+                                 hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (n > scan_max_elems()) return hipErrorInvalidValue;
+    int nt = scan_tiles(n);
+    k_scan_reduce<<<nt, SCAN_BS, 0, s>>>(in, (int)n, part);
+    k_scan_top<<<1, SCAN_TOP_BS, 0, s>>>(part, nt);
+    k_scan_apply<<<nt, SCAN_BS, 0, s>>>(in, out, (int)n, part, zero_in);
+    return hipGetLastError();
+}
+
+// Lanes of this wave whose 8-bit digit equals this lane's (valid lanes only).
+__device__ __forceinline__ uint64_t match_digit(unsigned d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(RS_BS) void k_radix_hist(const int *__restrict__ keys, int n,
+                                                      int shift, int *__restrict__ hist,
+                                                      int ntiles)
+{
+    __shared__ int h[RS_RADIX];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int64_t idx = tbase + r * RS_BS + tid;
+        const bool valid = idx < n;
+        const unsigned d = valid ? ((unsigned)keys[idx] >> shift) & 255u : 0u;
+        const uint64_t m = match_digit(d, valid);
+        if (valid && mbcnt(m) == 0) atomicAdd(&h[d], (int)__popcll(m));
+    }
+    __syncthreads();
+    hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+__global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__ kin,
+                                                         const int *__restrict__ vin, int n,
+                                                         int shift,
+                                                         const int *__restrict__ hist, int ntiles,
+                                                         int *__restrict__ kout,
+                                                         int *__restrict__ vout)
+{
+    __shared__ int base[RS_RADIX];
+    __shared__ int wc[RS_BS / 64][RS_RADIX];
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    base[tid] = hist[(int64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < RS_BS / 64; ++q) wc[q][tid] = 0;
+    __syncthreads();
+    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int64_t idx = tbase + r * RS_BS + tid;
+        const bool valid = idx < n;
+        const int key = valid ? kin[idx] : 0;
+        const int val = valid ? (vin ? vin[idx] : (int)idx) : 0;
+        const unsigned d = ((unsigned)key >> shift) & 255u;
+        const uint64_t m = match_digit(d, valid);
+        const int rk = mbcnt(m);
+        if (valid && rk == 0) wc[w][d] = (int)__popcll(m);
+        __syncthreads();
+        int pos = 0;
+        if (valid) {
+            pos = base[d] + rk;
+            for (int q = 0; q < w; ++q) pos += wc[q][d];
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int q = 0; q < RS_BS / 64; ++q) {
+            add += wc[q][tid];
+            wc[q][tid] = 0;
+        }
+        base[tid] += add;
+        if (valid) {
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+int radix_passes(int64_t ncells)
+{
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < ncells) ++bits;
+    return (bits + 7) / 8;
+}
+
+// Stable sort of indices 0..n-1 by keys[] (values < ncells).  Writes the
+// sorted keys to skey and the permutation to perm.  Scratch: k0, v0, k1, v1
+// (n ints each), hist (RS_RADIX * radix_tiles(n)), part (scan tiles).
+hipError_t launch_radix_sort(const int *keys, int64_t n, int64_t ncells, int *skey, int *perm,
+                             int *k0, int *v0, int *k1, int *v1, int *hist, int *part,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int nt = radix_tiles(n);
+    const int passes = radix_passes(ncells);
+    const int *kin = keys;
+    const int *vin = nullptr;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        int *ko, *vo;
+        if (p == passes - 1) { ko = skey; vo = perm; }
+        else if (p % 2 == 0) { ko = k0; vo = v0; }
+        else { ko = k1; vo = v1; }
+        k_radix_hist<<<nt, RS_BS, 0, s>>>(kin, (int)n, shift, hist, nt);
+        hipError_t e = launch_exclusive_scan(hist, hist, (int64_t)RS_RADIX * nt, part, 0, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<nt, RS_BS, 0, s>>>(kin, vin, (int)n, shift, hist, nt, ko, vo);
+        kin = ko;
+        vin = vo;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sphx
