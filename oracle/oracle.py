@@ -100,8 +100,14 @@ def lib():
             f.argtypes = ps
         L.or_step.restype = C.c_int
         L.or_step.argtypes = ps + [C.c_int]
+        L.or_num_threads.restype = C.c_int
+        L.or_num_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def num_threads():
+    return int(lib().or_num_threads())
 
 
 def W(dim, h, r):

@@ -40,10 +40,22 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Kernel                                                                   */
@@ -292,8 +304,9 @@ void or_density(const or_params *p, or_state *s, double dt)
         double rho_sum = p->mass * c.sigma;
         double rho_star = s->rho[i] + dt * c.drho;
         double excess = rho_star - rho_sum;
-        if (excess < 0.0) excess = 0.0;
-        double rho = rho_sum + excess * p->rho0 / rho_star;
+        /* the free-surface term max(0, rho* - rho_sum) rho0/rho* is zero
+         * unless the excess is positive (then rho* > rho_sum >= 0) */
+        double rho = (excess > 0.0) ? rho_sum + excess * p->rho0 / rho_star : rho_sum;
         double pr = p->c0 * p->c0 * (rho - p->rho0);
         if (pr < 0.0) pr = 0.0;
         s->rho[i] = rho;

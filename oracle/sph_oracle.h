@@ -62,6 +62,9 @@ typedef struct {
     int64_t *step;           /* [1] completed steps */
 } or_state;
 
+/* OpenMP threads the sweeps use. */
+int or_num_threads(void);
+
 /* Kernel and lattice constants. */
 double or_kernel_alpha(int dim, double h);
 double or_W(int dim, double h, double r);
