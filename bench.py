@@ -1,0 +1,287 @@
+"""Throughput of the WCSPH step on one MI355X.
+
+Default workload: the 3D dam break of 2.0 M fluid particles (1 x 1 x 2 m block
+at dx = 0.01 in a 4 x 1 x 3 m box, 1.17 M wall particles), plain FP64 path,
+arrays re-sorted by cell every 20 steps, 500 timed steps.  A step is the whole
+hot path: half kick + drift + cell keys, cell scan, radix sort, (reorder),
+sweep records, density sweep, force sweep fused with the second half kick,
+and the FP64 reductions for dt and the diagnostics.
+
+Prints one JSON line.  Besides the headline value it reports the roofline of
+the dominant kernel (algorithmic FLOPs per launch over its HIP-event time),
+the same workload on the mixed-precision path, and the CPU reference timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "M particle-updates/s (3D WCSPH step) + achieved HBM GB/s vs FP64 path"
+FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
+HBM_PEAK_GBS = 8000.0
+
+# FP64 flops per candidate test and per neighbour pair (viscosity excluded:
+# it runs on approaching pairs only, so leaving it out keeps the count a
+# lower bound).  Candidate: r = x_i - x_j, r^2.  Density pair: sqrt, q, t,
+# t^3, W, F, v_ij.r, two accumulations.  Force pair: sqrt, q, t, t^3, F,
+# v_ij.r, (P_i + P_j) F, two vector accumulations.
+FLOPS = {
+    2: {"cand": 5, "density": 20, "force": 24},
+    3: {"cand": 8, "density": 23, "force": 30},
+}
+
+WORKLOADS = {
+    "c2_3d": "3D WCSPH dam break: 1x1x2 m fluid block at dx=0.01 (2,000,000 fluid + "
+             "1,169,016 wall particles) in a 4x1x3 m box, Wendland C2 h=1.3dx, "
+             "re-sort every 20 steps",
+    "c3_3d": "3D WCSPH dam break: 1x1x2 m block at dx=0.005 (16,000,000 fluid + "
+             "4,617,816 wall particles) in a 4x1x3 m box",
+    "c5_3d": "3D WCSPH dam break: 2x2x2 m block at dx=0.0065 (29,218,112 fluid + "
+             "6,613,248 wall particles) in an 8x2x3 m box, re-sort every 50 steps",
+    "c4_batch": "64 independent 2D dam breaks, widths U[0.5,2] m, dx=0.005 "
+                "(8.37 M fluid particles in total), one launch per stage",
+    "c1_2d": "2D WCSPH dam break: 1x2 m column at dx=0.025 (3,200 fluid particles)",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def candidate_count(sim, h):
+    """Sum over fluid targets of the particles (fluid + wall) in their 3^d
+    stencil cells, minus the target itself: the candidates direct search tests."""
+    dim = sim.dim
+    cs = h["cell_start"].astype(np.int64)
+    ws = h["wall_start"].astype(np.int64)
+    occ = (cs[1:] - cs[:-1]) + (ws[1:] - ws[:-1])
+    total = 0
+    for b in range(sim.B):
+        f0, f1 = sim.fluid_offset[b], sim.fluid_offset[b + 1]
+        if f1 == f0:
+            continue
+        lo, nc, base = sim.grid(b)
+        nx, ny, nz = nc
+        occ_b = occ[base:base + nx * ny * nz].reshape(nz, ny, nx)
+        # 3^d box sum of occupancy with clamping at the grid edge
+        pad = np.pad(occ_b, ((1, 1) if dim == 3 else (0, 0), (1, 1), (1, 1)))
+        box = np.zeros_like(occ_b)
+        for dz in ((-1, 0, 1) if dim == 3 else (0,)):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    zz = slice(1 + dz, 1 + dz + nz) if dim == 3 else slice(0, nz)
+                    box += pad[zz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+        keys = h["key"][f0:f1].astype(np.int64) - base
+        total += int(box.reshape(-1)[keys].sum()) - (f1 - f0)
+    return total
+
+
+def kernel_source_hash():
+    hsh = hashlib.sha256()
+    for name in ("sph_kernels.hip", "sph_device.h"):
+        with open(os.path.join(ROOT, "paper_2603_11868_amd", "csrc", name), "rb") as f:
+            hsh.update(f.read())
+    return hsh.hexdigest()[:16]
+
+
+def load_traffic(workload, precision, kernel):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0, queue=0):
+    import torch
+    from paper_2603_11868_amd import sph
+
+    sim = sph.Simulation(case, precision=precision, reorder_every=reorder_every,
+                         use_graph=graph, block_threads=block, queue_cap=queue)
+    sim.prime()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    if timing:
+        sph.sph_set_timing(sim.ctx, 1)
+        sph.sph_stage_times(sim.ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = sph.sph_stage_times(sim.ctx, reset=True) if timing else {}
+    sph.sph_set_timing(sim.ctx, 0)
+    flags = sim.poll_errors()
+    h = sim.host()
+    return sim, h, t1 - t0, stages, flags
+
+
+def cpu_baseline(case, nsteps):
+    from oracle import oracle as O
+
+    ref = O.OracleSim.from_case(case)
+    ref.prime()
+    t0 = time.perf_counter()
+    ref.step(nsteps)
+    t1 = time.perf_counter()
+    return ref, case.n_fluid * nsteps / (t1 - t0) / 1e6, O.num_threads(), t1 - t0
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--case", default="c2_3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--compare", default="mixed", choices=("mixed", "fp64", "none"),
+                    help="second precision timed on the same workload")
+    ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--queue", type=int, default=0, help="sweep hit-queue capacity (-1: direct)")
+    ap.add_argument("--reorder-every", type=int, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps of the CPU sample (0: skip)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (PMC calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
+              "here is single-GPU and multi-GPU sharding is not built", file=sys.stderr)
+        return 2
+
+    import torch
+    import dambreak
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    case = dambreak.make_case(args.case)
+    n_fluid = case.n_fluid
+    log(f"case {args.case}: {n_fluid} fluid, {case.n_wall} wall; {args.precision}; "
+        f"steps {args.steps} warmup {args.warmup}")
+
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 8
+        a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    sim, h, secs, stages, flags = run_gpu(case, args.precision, args.steps, args.warmup,
+                                          args.graph, timing=not args.graph,
+                                          reorder_every=args.reorder_every, block=args.block,
+                                          queue=args.queue)
+    value = n_fluid * args.steps / secs / 1e6
+    log(f"{args.precision}: {secs * 1e3 / args.steps:.3f} ms/step, {value:.1f} M updates/s, flags {flags}")
+    for k, (ms, n) in stages.items():
+        if n:
+            log(f"  {k:12s} {ms / n * 1e3:9.1f} us x {n}")
+
+    # roofline of the dominant kernel
+    roof = None
+    if stages:
+        name, (ms, n) = max(stages.items(), key=lambda kv: kv[1][0])
+        avg_s = ms / n / 1e3
+        dim = case.dim
+        pairs = float(h["diag"][:, 12].sum())
+        cands = candidate_count(sim, h)
+        if name in ("density", "force"):
+            flops = FLOPS[dim]["cand"] * cands + FLOPS[dim][name] * pairs
+            achieved = flops / avg_s / 1e12
+            traffic = load_traffic(args.case, args.precision, name)
+            roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
+                    "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
+                    "traffic": traffic, "flops_per_launch": flops,
+                    "candidates": cands, "pairs": pairs, "avg_ms": round(avg_s * 1e3, 4)}
+            if traffic:
+                roof["hbm_gbs"] = round(traffic / avg_s / 1e9, 1)
+        else:
+            roof = {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": None, "traffic": None, "avg_ms": round(avg_s * 1e3, 4)}
+    stage_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages.items() if n}
+    state_fp = {"x": h["x"], "v": h["v"], "rho": h["rho"], "id": h["id"]}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    other = None
+    if args.compare != "none" and args.compare != args.precision:
+        sim2, h2, secs2, stages2, flags2 = run_gpu(case, args.compare, args.steps, args.warmup,
+                                                   False, timing=True,
+                                                   reorder_every=args.reorder_every,
+                                                   block=args.block, queue=args.queue)
+        v2 = n_fluid * args.steps / secs2 / 1e6
+        # difference between the two precisions after the same steps, by particle id
+        def by_id(st):
+            out = {}
+            for k in ("x", "v", "rho"):
+                arr = np.empty_like(st[k])
+                arr[st["id"]] = st[k]
+                out[k] = arr
+            return out
+        a_, b_ = by_id(state_fp), by_id({"x": h2["x"], "v": h2["v"], "rho": h2["rho"], "id": h2["id"]})
+        other = {
+            "precision": args.compare, "value": round(v2, 2),
+            "ms_per_step": round(secs2 * 1e3 / args.steps, 4),
+            "ratio_vs_headline": round(v2 / value, 3),
+            "stage_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages2.items() if n},
+            "diff_vs_headline_after_run": {
+                "rho_rel": float(np.abs(a_["rho"] - b_["rho"]).max() / case.rho0),
+                "v_rel": float(np.abs(a_["v"] - b_["v"]).max() / max(np.abs(a_["v"]).max(), 1e-300)),
+                "x_abs_over_dx": float(np.abs(a_["x"] - b_["x"]).max() / case.dx),
+            },
+            "flags": flags2,
+        }
+        log(f"{args.compare}: {secs2 * 1e3 / args.steps:.3f} ms/step, {v2:.1f} M updates/s")
+        sim2.close()
+        del sim2
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if args.cpu_steps > 0:
+        _, cv, cores, csecs = cpu_baseline(case, args.cpu_steps)
+        cpu = {"value": round(cv, 4), "unit": "M particle-updates/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{args.case}: FP64 CPU reference, prime + {args.cpu_steps} full "
+                         f"steps of all {n_fluid} fluid particles ({csecs:.1f} s)"}
+        log(f"cpu oracle: {cv:.3f} M updates/s on {cores} threads ({csecs:.1f} s)")
+
+    dtype = "f64" if args.precision == "fp64" else "f32+f64"
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "M particle-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(secs * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.case], "case": args.case,
+                   "precision": args.precision, "n_fluid": n_fluid, "n_wall": case.n_wall,
+                   "reorder_every": case.reorder_every if args.reorder_every is None else args.reorder_every,
+                   "graph": bool(args.graph), "block_threads": args.block or 256,
+                   "queue_cap": args.queue or 32},
+        "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
+        "compare": other, "flags": flags,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -109,7 +109,9 @@ typedef struct {
     double g[3];             /* gravity */
     const sph_instance_desc *inst;   /* n_instances entries (copied) */
     int32_t block_threads;   /* threads per sweep block: 0 (default 256), 64, 128, 256 */
-    int32_t queue_cap;       /* per-thread neighbour queue of the sweeps: 0 = default */
+    int32_t queue_cap;       /* per-thread hit queue of the sweeps (LDS entries):
+                                0 = default (32), 16 or 32; -1 = plain direct
+                                search without compaction */
     int32_t use_graph;       /* sph_step_batched replays captured HIP graphs */
     int32_t reserved[5];
 } sph_params;

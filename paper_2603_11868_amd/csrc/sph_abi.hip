@@ -89,6 +89,7 @@ struct sph_ctx {
     std::vector<Chunk> fmap, wmap;
     int64_t N = 0, Nw = 0, C = 0;
     int block = 256;
+    int qcap = 32;
     bool mixed = false;
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
@@ -363,10 +364,13 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
         return fail(SPH_E_ARG, "alpha >= 0, eps > 0 and positive Courant numbers required");
     const int block = p->block_threads == 0 ? 256 : p->block_threads;
     if (block != 64 && block != 128 && block != 256) return fail(SPH_E_ARG, "block_threads must be 0, 64, 128 or 256");
+    const int qcap = p->queue_cap == 0 ? 32 : (p->queue_cap < 0 ? 0 : p->queue_cap);
+    if (qcap != 0 && qcap != 16 && qcap != 32) return fail(SPH_E_ARG, "queue_cap must be -1, 0, 16 or 32");
     auto *c = new sph_ctx();
     c->p = *p;
     c->p.inst = nullptr;
     c->block = block;
+    c->qcap = qcap;
     c->mixed = p->precision == SPH_MIXED;
     c->inst.assign(p->inst, p->inst + p->n_instances);
     const double cs = 2.0 * p->h;
@@ -390,6 +394,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     }
     if (N >= INT32_MAX || Nw >= INT32_MAX || C >= INT32_MAX - 1) { delete c; return fail(SPH_E_CAPACITY, "more than 2^31 particles or cells"); }
     if (C + 1 > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many cells for the two-level scan"); }
+    if (qcap > 0 && (N >= (1 << 26) || Nw >= (1 << 26))) { delete c; return fail(SPH_E_CAPACITY, "queued sweeps address at most 2^26 particles per kind; use queue_cap = -1"); }
     if ((int64_t)256 * radix_tiles(std::max(N, Nw)) > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many particles for the radix histogram scan"); }
     c->N = N;
     c->Nw = Nw;
@@ -522,7 +527,7 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.nfchunks = (int)c->fmap.size();
     d.nwchunks = (int)c->wmap.size();
     d.block = c->block;
-    d.queue_cap = c->p.queue_cap;
+    d.queue_cap = c->qcap;
     if (!c->fmap.empty())
         HIP_TRY(hipMemcpyAsync(d.fmap, c->fmap.data(), sizeof(Chunk) * c->fmap.size(), hipMemcpyHostToDevice, s));
     if (!c->wmap.empty())

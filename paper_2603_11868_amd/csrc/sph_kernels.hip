@@ -369,9 +369,8 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
             const int yy = cy + dy;
             if (yy < 0 || yy >= ncy) continue;
             const int row = I.cell_base + (yy + ncy * (cz + dz)) * ncx;
-            real tx0 = 0, ty = 0, tz = 0;
+            real ty = 0, tz = 0;
             if constexpr (MIXED) {
-                tx0 = pi.x - (real)(xlo - cx) * cs;
                 ty = pi.y - (real)dy * cs;
                 if constexpr (DIM == 3) tz = pi.z - (real)dz * cs;
             }
@@ -391,8 +390,8 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
                     const auto pj = src[s];
                     real r[3];
                     if constexpr (MIXED) {
-                        const real tx = s < b1 ? tx0 : (s < b2 ? tx0 - cs : tx0 - 2 * cs);
-                        r[0] = tx - pj.x;
+                        const int ox = xlo - cx + (s >= b1) + (s >= b2);
+                        r[0] = (pi.x - (real)ox * cs) - pj.x;
                         r[1] = ty - pj.y;
                         if constexpr (DIM == 3) r[2] = tz - pj.z;
                     } else {
@@ -430,11 +429,148 @@ __device__ __forceinline__ void kernel_F(real r2, real inv_h, real kF, real &F)
     F = kF * t * t * t;
 }
 
+__device__ __forceinline__ int wave_max_int(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Queue entries: source slot (26 bits), stencil cell code (5 bits), wall flag.
+constexpr int kQueueSlotBits = 26;
+constexpr unsigned kQueueSlotMask = (1u << kQueueSlotBits) - 1u;
+
+// Neighbour traversal with per-lane compaction.  Phase 1 tests candidates in
+// wave-uniform loops (lanes past the end of their own range are predicated
+// off) and appends every hit to the lane's queue in LDS; whenever a lane's
+// queue is full, and once at the end, the wave drains all queues together,
+// so the pair arithmetic runs on dense work instead of on every candidate
+// where any lane of the wave has a hit.  Hits are drained in the order they
+// were found, so the sums run in the same order as the direct traversal.
+template <int DIM, bool MIXED, int Q, class Fn>
+__device__ __forceinline__ void for_neighbours_queued(
+    const SimConst &sc, const InstDev &I, bool act, int lk, int k,
+    const typename Rec<DIM, MIXED>::pos_t &pi, const int *__restrict__ cstart,
+    const int *__restrict__ wstart, const typename Rec<DIM, MIXED>::pos_t *__restrict__ pos,
+    const typename Rec<DIM, MIXED>::pos_t *__restrict__ wpos, unsigned (*__restrict__ q)[kMaxBlock],
+    Fn &&fn)
+{
+    using real = typename Rec<DIM, MIXED>::real;
+    const int tid = threadIdx.x;
+    const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
+    int cx = 0, cy = 0, cz = 0;
+    if (act) {
+        cx = lk % ncx;
+        const int tq = lk / ncx;
+        cy = tq % ncy;
+        cz = tq / ncy;
+    }
+    const int xlo = cx > 0 ? cx - 1 : 0;
+    const int xhi = cx < ncx - 1 ? cx + 1 : ncx - 1;
+    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
+    const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
+    int len = 0;
+
+    auto pair_vector = [&](const typename Rec<DIM, MIXED>::pos_t &pj, int code, real *r) {
+        if constexpr (MIXED) {
+            const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
+            r[0] = (pi.x - (real)ox * cs) - pj.x;
+            r[1] = (pi.y - (real)oy * cs) - pj.y;
+            if constexpr (DIM == 3) r[2] = (pi.z - (real)oz * cs) - pj.z;
+        } else {
+            (void)code;
+            r[0] = pi.x - pj.x;
+            r[1] = pi.y - pj.y;
+            if constexpr (DIM == 3) r[2] = pi.z - pj.z;
+        }
+    };
+    auto drain = [&]() {
+        const int m = wave_max_int(len);
+        for (int t = 0; t < m; ++t) {
+            if (t < len) {
+                const unsigned e = q[t][tid];
+                const bool wall = (e >> 31) != 0u;
+                const int s = (int)(e & kQueueSlotMask);
+                const int code = (int)((e >> kQueueSlotBits) & 31u);
+                const auto pj = wall ? wpos[s] : pos[s];
+                real r[3];
+                pair_vector(pj, code, r);
+                real r2;
+                if constexpr (DIM == 3) r2 = dist2(r[0], r[1], r[2]);
+                else r2 = dist2(r[0], r[1]);
+                fn(wall, s, r, r2);
+            }
+        }
+        len = 0;
+    };
+
+    const int dz_first = DIM == 3 ? -1 : 0, dz_last = DIM == 3 ? 1 : 0;
+    for (int dz = dz_first; dz <= dz_last; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = cy + dy, zz = cz + dz;
+            const bool row_ok = act && yy >= 0 && yy < ncy && zz >= 0 && zz < ncz;
+            const int row = I.cell_base + (yy + ncy * zz) * ncx;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int *__restrict__ st = pass == 0 ? cstart : wstart;
+                const typename Rec<DIM, MIXED>::pos_t *__restrict__ src = pass == 0 ? pos : wpos;
+                int s0 = 0, s1 = 0, b1 = 0, b2 = 0;
+                if (row_ok) {
+                    s0 = st[row + xlo];
+                    s1 = st[row + xhi + 1];
+                    b1 = xlo + 1 <= xhi ? st[row + xlo + 1] : s1;
+                    b2 = xlo + 2 <= xhi ? st[row + xlo + 2] : s1;
+                }
+                const int n = s1 - s0;
+                const int nmax = wave_max_int(n);
+                const unsigned wall_bit = pass == 1 ? 0x80000000u : 0u;
+                const int code_base = ((dz + 1) * 3 + (dy + 1)) * 3 + (xlo - cx + 1);
+                for (int t = 0; t < nmax; ++t) {
+                    const int s = s0 + t;
+                    if (t < n && !(pass == 0 && s == k)) {
+                        const auto pj = src[s];
+                        const int xi = (s >= b1) + (s >= b2);      // cell within the row
+                        const int code = code_base + xi;
+                        real r[3];
+                        pair_vector(pj, code, r);
+                        real r2;
+                        if constexpr (DIM == 3) r2 = dist2(r[0], r[1], r[2]);
+                        else r2 = dist2(r[0], r[1]);
+                        if (r2 < cut2) {
+                            q[len][tid] = wall_bit | ((unsigned)code << kQueueSlotBits) | (unsigned)s;
+                            ++len;
+                        }
+                    }
+                    if (__ballot(len == Q)) drain();
+                }
+            }
+        }
+    }
+    drain();
+}
+
+// Traversal dispatch: Q == 0 is the plain direct search, Q > 0 the queued one.
+template <int DIM, bool MIXED, int Q, class Fn>
+__device__ __forceinline__ void traverse(const SimConst &sc, const InstDev &I, bool act, int lk, int k,
+                                         const typename Rec<DIM, MIXED>::pos_t &pi,
+                                         const int *__restrict__ cstart, const int *__restrict__ wstart,
+                                         const typename Rec<DIM, MIXED>::pos_t *__restrict__ pos,
+                                         const typename Rec<DIM, MIXED>::pos_t *__restrict__ wpos,
+                                         unsigned (*__restrict__ q)[kMaxBlock], Fn &&fn)
+{
+    if constexpr (Q == 0) {
+        (void)q;
+        if (act) for_neighbours<DIM, MIXED>(sc, I, lk, k, pi, cstart, wstart, pos, wpos, fn);
+    } else {
+        for_neighbours_queued<DIM, MIXED, Q>(sc, I, act, lk, k, pi, cstart, wstart, pos, wpos, q, fn);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // density sweep
 // ---------------------------------------------------------------------------
 
-template <int DIM, bool MIXED>
+template <int DIM, bool MIXED, int Q>
 __global__ __launch_bounds__(kMaxBlock) void k_density(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
@@ -446,20 +582,23 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
 {
     using R = Rec<DIM, MIXED>;
     using real = typename R::real;
+    __shared__ unsigned q[Q > 0 ? Q : 1][kMaxBlock];
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
-    if (k >= ch.end) return;
+    const bool act = k < ch.end;
+    if (Q == 0 && !act) return;
     const InstDev &I = inst[ch.inst];
-    const int lk = skey[k] - I.cell_base;
-    const typename R::pos_t pi = pos[k];
-    const typename R::vel_t vi = vel[k];
+    const int kk = act ? k : ch.begin;
+    const int lk = skey[kk] - I.cell_base;
+    const typename R::pos_t pi = pos[kk];
+    const typename R::vel_t vi = vel[kk];
     const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
     const real kW = MIXED ? (real)sc.fkW : (real)sc.kW;
     const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
     real sigma = MIXED ? (real)0 : (real)sc.W0;
     real drho = 0;
     int cnt = 0;
-    for_neighbours<DIM, MIXED>(sc, I, lk, k, pi, cstart, wstart, pos, wpos,
+    traverse<DIM, MIXED, Q>(sc, I, act, lk, k, pi, cstart, wstart, pos, wpos, q,
         [&](bool wall, int s, const real *r, real r2) {
             real W, F;
             kernel_WF(r2, inv_h, kW, kF, W, F);
@@ -476,6 +615,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
             drho += vr * F;
             ++cnt;
         });
+    if (!act) return;
     const int i = perm[k];
     const double sig = MIXED ? sc.W0 + (double)sigma : (double)sigma;
     const double rho_sum = sc.mass * sig;
@@ -494,22 +634,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     rp[k] = out;
 }
 
-template <int DIM, bool MIXED>
+template <int DIM, bool MIXED, int Q>
 static void density_dispatch(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
 {
     using R = Rec<DIM, MIXED>;
-    k_density<DIM, MIXED><<<d.nfchunks, d.block, 0, s>>>(
+    k_density<DIM, MIXED, Q><<<d.nfchunks, d.block, 0, s>>>(
         sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start,
         static_cast<const typename R::pos_t *>(d.pos), static_cast<const typename R::vel_t *>(d.vel),
         static_cast<const typename R::pos_t *>(d.wpos), d.rho, d.count,
         static_cast<typename R::rp_t *>(d.rp), d.dt, use_dt);
 }
 
+template <int DIM, bool MIXED>
+static void density_q(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
+{
+    if (d.queue_cap == 0) density_dispatch<DIM, MIXED, 0>(sc, d, use_dt, s);
+    else if (d.queue_cap == 16) density_dispatch<DIM, MIXED, 16>(sc, d, use_dt, s);
+    else density_dispatch<DIM, MIXED, 32>(sc, d, use_dt, s);
+}
+
 hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s)
 {
     if (d.nfchunks <= 0) return hipSuccess;
-    if (sc.dim == 2) { if (mixed) density_dispatch<2, true>(sc, d, use_dt, s); else density_dispatch<2, false>(sc, d, use_dt, s); }
-    else { if (mixed) density_dispatch<3, true>(sc, d, use_dt, s); else density_dispatch<3, false>(sc, d, use_dt, s); }
+    if (sc.dim == 2) { if (mixed) density_q<2, true>(sc, d, use_dt, s); else density_q<2, false>(sc, d, use_dt, s); }
+    else { if (mixed) density_q<3, true>(sc, d, use_dt, s); else density_q<3, false>(sc, d, use_dt, s); }
     return hipGetLastError();
 }
 
@@ -575,7 +723,7 @@ __device__ __forceinline__ void state_partials(const SimConst &sc, const InstDev
 // force sweep (+ half 2 and partials when fused)
 // ---------------------------------------------------------------------------
 
-template <int DIM, bool MIXED, bool FUSED>
+template <int DIM, bool MIXED, bool FUSED, int Q>
 __global__ __launch_bounds__(kMaxBlock) void k_force(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
@@ -588,64 +736,66 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
 {
     using R = Rec<DIM, MIXED>;
     using real = typename R::real;
+    __shared__ unsigned q[Q > 0 ? Q : 1][kMaxBlock];
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     const bool act = k < ch.end;
     const InstDev &I = inst[ch.inst];
     double vals[kNPart];
 #pragma unroll
-    for (int q = 0; q < kNPart; ++q) vals[q] = 0.0;
+    for (int qq = 0; qq < kNPart; ++qq) vals[qq] = 0.0;
+    const int kk = act ? k : ch.begin;
+    const int lk = skey[kk] - I.cell_base;
+    const typename R::pos_t pi = pos[kk];
+    const typename R::vel_t vi = vel[kk];
+    const typename R::rp_t rpi = rp[kk];
+    const real rho_i = rpi.x, P_i = rpi.y;
+    const real p_i = P_i * rho_i * rho_i;
+    const real inv_rho_i2 = (real)1 / (rho_i * rho_i);
+    const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
+    const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
+    const real visc_a = (real)(sc.alpha * I.c0 * sc.h);
+    const real eps_h2 = MIXED ? (real)sc.feps_h2 : (real)sc.eps_h2;
+    const real gx = MIXED ? (real)sc.fg[0] : (real)sc.g[0];
+    const real gy = MIXED ? (real)sc.fg[1] : (real)sc.g[1];
+    const real gz = MIXED ? (real)sc.fg[2] : (real)sc.g[2];
+    real acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
+    int cnt = 0;
+    traverse<DIM, MIXED, Q>(sc, I, act, lk, k, pi, cstart, wstart, pos, wpos, q,
+        [&](bool wall, int s, const real *r, real r2) {
+            real F;
+            kernel_F(r2, inv_h, kF, F);
+            real P_j, rho_j, vr;
+            if (wall) {
+                real gr = gx * r[0] + gy * r[1];
+                if constexpr (DIM == 3) gr += gz * r[2];
+                real p_j = p_i - rho_i * gr;       // p_i + rho_i g.(x_j - x_i)
+                if (p_j < (real)0) p_j = (real)0;
+                P_j = p_j * inv_rho_i2;
+                rho_j = rho_i;
+                vr = vi.x * r[0] + vi.y * r[1];
+                if constexpr (DIM == 3) vr += vi.z * r[2];
+            } else {
+                const typename R::rp_t rpj = rp[s];
+                const typename R::vel_t vj = vel[s];
+                rho_j = rpj.x;
+                P_j = rpj.y;
+                vr = (vi.x - vj.x) * r[0] + (vi.y - vj.y) * r[1];
+                if constexpr (DIM == 3) vr += (vi.z - vj.z) * r[2];
+            }
+            real visc = 0;
+            if (vr < (real)0)
+                visc = -visc_a * vr / ((real)0.5 * (rho_i + rho_j) * (r2 + eps_h2));
+            const real coef = (P_i + P_j + visc) * F;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc[c] -= coef * r[c];
+            if (!wall) {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) aff[c] -= coef * r[c];
+            }
+            ++cnt;
+        });
     if (act) {
-        const int lk = skey[k] - I.cell_base;
-        const typename R::pos_t pi = pos[k];
-        const typename R::vel_t vi = vel[k];
-        const typename R::rp_t rpi = rp[k];
-        const real rho_i = rpi.x, P_i = rpi.y;
-        const real p_i = P_i * rho_i * rho_i;
-        const real inv_rho_i2 = (real)1 / (rho_i * rho_i);
-        const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
-        const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
-        const real visc_a = (real)(sc.alpha * I.c0 * sc.h);
-        const real eps_h2 = MIXED ? (real)sc.feps_h2 : (real)sc.eps_h2;
-        const real gx = MIXED ? (real)sc.fg[0] : (real)sc.g[0];
-        const real gy = MIXED ? (real)sc.fg[1] : (real)sc.g[1];
-        const real gz = MIXED ? (real)sc.fg[2] : (real)sc.g[2];
-        real acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
-        int cnt = 0;
-        for_neighbours<DIM, MIXED>(sc, I, lk, k, pi, cstart, wstart, pos, wpos,
-            [&](bool wall, int s, const real *r, real r2) {
-                real F;
-                kernel_F(r2, inv_h, kF, F);
-                real P_j, rho_j, vr;
-                if (wall) {
-                    real gr = gx * r[0] + gy * r[1];
-                    if constexpr (DIM == 3) gr += gz * r[2];
-                    real p_j = p_i - rho_i * gr;       // p_i + rho_i g.(x_j - x_i)
-                    if (p_j < (real)0) p_j = (real)0;
-                    P_j = p_j * inv_rho_i2;
-                    rho_j = rho_i;
-                    vr = vi.x * r[0] + vi.y * r[1];
-                    if constexpr (DIM == 3) vr += vi.z * r[2];
-                } else {
-                    const typename R::rp_t rpj = rp[s];
-                    const typename R::vel_t vj = vel[s];
-                    rho_j = rpj.x;
-                    P_j = rpj.y;
-                    vr = (vi.x - vj.x) * r[0] + (vi.y - vj.y) * r[1];
-                    if constexpr (DIM == 3) vr += (vi.z - vj.z) * r[2];
-                }
-                real visc = 0;
-                if (vr < (real)0)
-                    visc = -visc_a * vr / ((real)0.5 * (rho_i + rho_j) * (r2 + eps_h2));
-                const real coef = (P_i + P_j + visc) * F;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) acc[c] -= coef * r[c];
-                if (!wall) {
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) aff[c] -= coef * r[c];
-                }
-                ++cnt;
-            });
         const int i = perm[k];
         double an[DIM];
 #pragma unroll
@@ -672,26 +822,34 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     else block_partials<P_FF, P_PAIRS + 1>(vals, out);
 }
 
-template <int DIM, bool MIXED, bool FUSED>
+template <int DIM, bool MIXED, bool FUSED, int Q>
 static void force_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
 {
     using R = Rec<DIM, MIXED>;
-    k_force<DIM, MIXED, FUSED><<<d.nfchunks, d.block, 0, s>>>(
+    k_force<DIM, MIXED, FUSED, Q><<<d.nfchunks, d.block, 0, s>>>(
         sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start,
         static_cast<const typename R::pos_t *>(d.pos), static_cast<const typename R::vel_t *>(d.vel),
         static_cast<const typename R::pos_t *>(d.wpos), static_cast<const typename R::rp_t *>(d.rp),
         d.a, d.v, d.x, d.rho, d.dt, d.partials, sc.N);
 }
 
+template <int DIM, bool MIXED, bool FUSED>
+static void force_q(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    if (d.queue_cap == 0) force_dispatch<DIM, MIXED, FUSED, 0>(sc, d, s);
+    else if (d.queue_cap == 16) force_dispatch<DIM, MIXED, FUSED, 16>(sc, d, s);
+    else force_dispatch<DIM, MIXED, FUSED, 32>(sc, d, s);
+}
+
 hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, hipStream_t s)
 {
     if (d.nfchunks <= 0) return hipSuccess;
     if (sc.dim == 2) {
-        if (mixed) { if (fused) force_dispatch<2, true, true>(sc, d, s); else force_dispatch<2, true, false>(sc, d, s); }
-        else { if (fused) force_dispatch<2, false, true>(sc, d, s); else force_dispatch<2, false, false>(sc, d, s); }
+        if (mixed) { if (fused) force_q<2, true, true>(sc, d, s); else force_q<2, true, false>(sc, d, s); }
+        else { if (fused) force_q<2, false, true>(sc, d, s); else force_q<2, false, false>(sc, d, s); }
     } else {
-        if (mixed) { if (fused) force_dispatch<3, true, true>(sc, d, s); else force_dispatch<3, true, false>(sc, d, s); }
-        else { if (fused) force_dispatch<3, false, true>(sc, d, s); else force_dispatch<3, false, false>(sc, d, s); }
+        if (mixed) { if (fused) force_q<3, true, true>(sc, d, s); else force_q<3, true, false>(sc, d, s); }
+        else { if (fused) force_q<3, false, true>(sc, d, s); else force_q<3, false, false>(sc, d, s); }
     }
     return hipGetLastError();
 }

@@ -1,0 +1,117 @@
+"""Autotuner for the launch parameters of the hot path.
+
+Searches threads per sweep block, the per-thread hit-queue capacity of the
+sweeps (or plain direct search), and the reorder period K (how often the
+state arrays are physically re-sorted by cell; the cell table itself is
+rebuilt every step, so K changes results only through summation order).
+Each variant runs whole steps through the C ABI and is timed with HIP events
+on the stream; the fastest is cached in a JSON file keyed by
+(arch, dim, precision, particle-count bucket).
+
+Command line:  python -m paper_2603_11868_amd.tune --case c2_3d --precision fp64
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import math
+import os
+import time
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+BLOCKS = (64, 128, 256)
+QUEUES = (-1, 16, 32)
+REORDERS = (1, 5, 20, 50)
+
+
+def cache_key(arch, dim, precision, n_fluid):
+    bucket = int(math.log2(max(n_fluid, 1)))
+    return f"{arch}/d{dim}/{precision}/n2^{bucket}"
+
+
+def time_variant(case, precision, block, queue, reorder, steps, warmup):
+    import torch
+    from .sph import Simulation
+
+    sim = Simulation(case, precision=precision, block_threads=block, queue_cap=queue,
+                     reorder_every=reorder)
+    try:
+        sim.prime()
+        sim.step(warmup)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        sim.step(steps)
+        stop.record()
+        torch.cuda.synchronize()
+        flags = sim.poll_errors()
+        return start.elapsed_time(stop) / steps, flags
+    finally:
+        sim.close()
+
+
+def tune(case, precision="fp64", steps=20, warmup=3, blocks=BLOCKS, queues=QUEUES,
+         reorders=REORDERS, cache_path=DEFAULT_CACHE, log=print):
+    """Time every variant; return the fastest as a dict and store it."""
+    import torch
+
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    results = []
+    for block, queue, reorder in itertools.product(blocks, queues, reorders):
+        ms, flags = time_variant(case, precision, block, queue, reorder, steps, warmup)
+        results.append({"block_threads": block, "queue_cap": queue, "reorder_every": reorder,
+                        "ms_per_step": round(ms, 5), "flags": flags})
+        if log:
+            log(f"  block {block:3d} queue {queue:3d} K {reorder:3d}: {ms:8.4f} ms/step")
+    ok = [r for r in results if r["flags"] == 0]
+    best = min(ok or results, key=lambda r: r["ms_per_step"])
+    key = cache_key(arch, case.dim, precision, case.n_fluid)
+    entry = {"best": best, "case": case.name, "n_fluid": case.n_fluid, "steps": steps,
+             "when": time.strftime("%Y-%m-%d %H:%M:%S"), "all": results}
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[key] = entry
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return entry
+
+
+def lookup(case, precision, arch="gfx950", cache_path=DEFAULT_CACHE):
+    """Cached best launch parameters for a workload, or None."""
+    if not os.path.exists(cache_path):
+        return None
+    with open(cache_path) as f:
+        cache = json.load(f)
+    e = cache.get(cache_key(arch, case.dim, precision, case.n_fluid))
+    return e["best"] if e else None
+
+
+def main(argv=None):
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import dambreak
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--case", default="c2_3d")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--blocks", default=",".join(map(str, BLOCKS)))
+    ap.add_argument("--queues", default=",".join(map(str, QUEUES)))
+    ap.add_argument("--reorders", default=",".join(map(str, REORDERS)))
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    args = ap.parse_args(argv)
+    case = dambreak.make_case(args.case)
+    ints = lambda s: tuple(int(v) for v in s.split(","))
+    e = tune(case, args.precision, args.steps, args.warmup, ints(args.blocks), ints(args.queues),
+             ints(args.reorders), args.cache)
+    print(json.dumps({"case": args.case, "precision": args.precision, "best": e["best"]}))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point the header declares, validates its arguments and derives
+the same grid and lattice constants as the CPU reference."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import dambreak
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sphmod():
+    from paper_2603_11868_amd import sph, _build
+    if not os.path.exists(sph.LIB_PATH):
+        _build.build()
+    sph.lib()
+    return sph
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "sph.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(sphmod):
+    names = header_functions()
+    assert len(names) >= 19
+    L = sphmod.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(sphmod.SYMBOLS)
+
+
+def _params(sphmod, case, **over):
+    B = len(case.instances)
+    descs = (sphmod.sph_instance_desc * B)()
+    for b, inst in enumerate(case.instances):
+        descs[b].n_fluid = inst.n_fluid
+        descs[b].n_wall = inst.n_wall
+        for a in range(3):
+            descs[b].tank_lo[a] = inst.tank_lo[a]
+            descs[b].tank_hi[a] = inst.tank_hi[a]
+        descs[b].c0 = inst.c0
+    p = sphmod.sph_params()
+    p.dim, p.precision, p.n_instances, p.reorder_every = case.dim, 0, B, case.reorder_every
+    p.dx, p.h, p.rho0, p.alpha, p.eps, p.cfl_ac, p.cfl_f = (case.dx, case.h, case.rho0, case.alpha,
+                                                          case.eps, case.cfl_ac, case.cfl_f)
+    for a in range(3):
+        p.g[a] = case.g[a]
+    p.inst = descs
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p, descs
+
+
+@pytest.mark.parametrize("name", ["c1_2d", "tiny_3d", "small_batch", "c2_3d"])
+def test_derived_grid_and_constants_match_reference(sphmod, name):
+    case = dambreak.make_case(name)
+    p, descs = _params(sphmod, case)
+    ctx = sphmod.sph_create(p)
+    try:
+        info = sphmod.sph_get_info(ctx)
+        assert info.n_fluid == case.n_fluid and info.n_wall == case.n_wall
+        base = 0
+        for b, inst in enumerate(case.instances):
+            ref = O.OracleSim(case.dim, case.dx, case.h, inst.tank_lo, inst.tank_hi,
+                              inst.fluid[:2], inst.wall[:2], inst.c0)
+            lo, nc, cb = sphmod.sph_get_grid(ctx, b)
+            assert nc == ref.ncell and cb == base
+            assert lo[:case.dim] == ref.lo[:case.dim]
+            base += ref.ncells
+            assert info.sigma0 == pytest.approx(ref.sigma0, rel=1e-14)
+            assert info.mass == pytest.approx(ref.mass, rel=1e-14)
+        assert info.n_cells == base
+        assert info.cell_size == 2 * case.h
+        assert info.workspace_bytes > 0 and sphmod.sph_workspace_size(ctx) == info.workspace_bytes
+    finally:
+        sphmod.sph_destroy(ctx)
+
+
+def test_argument_validation(sphmod):
+    case = dambreak.make_case("tiny_2d")
+    bad = [dict(dim=4), dict(precision=7), dict(n_instances=0), dict(dx=0.0), dict(h=-1.0),
+           dict(block_threads=100), dict(reorder_every=-1), dict(eps=0.0)]
+    for over in bad:
+        p, descs = _params(sphmod, case, **over)
+        with pytest.raises(sphmod.SphError, match="SPH_E_ARG"):
+            sphmod.sph_create(p)
+    p, descs = _params(sphmod, case)
+    descs[0].c0 = 0.0
+    with pytest.raises(sphmod.SphError, match="SPH_E_ARG"):
+        sphmod.sph_create(p)
+    p, descs = _params(sphmod, case)
+    descs[0].n_fluid = -3
+    with pytest.raises(sphmod.SphError, match="SPH_E_ARG"):
+        sphmod.sph_create(p)
+    assert "negative" in sphmod.sph_last_error()
+
+
+def test_calls_before_bind_are_rejected(sphmod):
+    case = dambreak.make_case("tiny_2d")
+    p, descs = _params(sphmod, case)
+    ctx = sphmod.sph_create(p)
+    try:
+        for fn in (sphmod.sph_prime, sphmod.sph_build_cells, sphmod.sph_density, sphmod.sph_forces):
+            with pytest.raises(sphmod.SphError, match="SPH_E_STATE"):
+                fn(ctx, 0)
+        with pytest.raises(sphmod.SphError, match="SPH_E_STATE"):
+            sphmod.sph_step_batched(ctx, 1, 0)
+        with pytest.raises(sphmod.SphError, match="SPH_E_ARG"):
+            sphmod.sph_step_batched(ctx, -1, 0)
+        with pytest.raises(sphmod.SphError, match="SPH_E_ARG"):
+            sphmod.sph_get_grid(ctx, 5)
+    finally:
+        sphmod.sph_destroy(ctx)
+    sphmod.sph_destroy(None)
+
+
+def test_stage_names(sphmod):
+    n = sphmod.sph_stage_count()
+    names = [sphmod.sph_stage_name(i) for i in range(n)]
+    assert names[:2] == ["keys", "cell_scan"] and "density" in names and "force" in names
+    assert sphmod.sph_stage_name(n) == ""
+
+
+def test_product_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2603_11868_amd import sph
+    monkeypatch.setattr(sph, "_lib", None)
+    monkeypatch.setattr(sph, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        sph.lib()
