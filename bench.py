@@ -108,12 +108,14 @@ def load_traffic(workload, precision, kernel):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0, queue=0):
+def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0, queue=0,
+            list_cap=0):
     import torch
     from paper_2603_11868_amd import sph
 
     sim = sph.Simulation(case, precision=precision, reorder_every=reorder_every,
-                         use_graph=graph, block_threads=block, queue_cap=queue)
+                         use_graph=graph, block_threads=block, queue_cap=queue,
+                         list_cap=list_cap)
     sim.prime()
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -155,6 +157,7 @@ def main(argv=None):
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--queue", type=int, default=0, help="sweep hit-queue capacity (-1: direct)")
+    ap.add_argument("--list", type=int, default=0, help="neighbour-list capacity (-1: no list)")
     ap.add_argument("--reorder-every", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps of the CPU sample (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -188,7 +191,7 @@ def main(argv=None):
     sim, h, secs, stages, flags = run_gpu(case, args.precision, args.steps, args.warmup,
                                           args.graph, timing=not args.graph,
                                           reorder_every=args.reorder_every, block=args.block,
-                                          queue=args.queue)
+                                          queue=args.queue, list_cap=args.list)
     value = n_fluid * args.steps / secs / 1e6
     log(f"{args.precision}: {secs * 1e3 / args.steps:.3f} ms/step, {value:.1f} M updates/s, flags {flags}")
     for k, (ms, n) in stages.items():
@@ -210,8 +213,8 @@ def main(argv=None):
             roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
-                    "traffic": traffic, "flops_per_launch": flops,
-                    "candidates": cands, "pairs": pairs, "avg_ms": round(avg_s * 1e3, 4)}
+                    "traffic": traffic, "flops_per_launch": float(flops),
+                    "candidates": int(cands), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
             if traffic:
                 roof["hbm_gbs"] = round(traffic / avg_s / 1e9, 1)
         else:
@@ -228,7 +231,8 @@ def main(argv=None):
         sim2, h2, secs2, stages2, flags2 = run_gpu(case, args.compare, args.steps, args.warmup,
                                                    False, timing=True,
                                                    reorder_every=args.reorder_every,
-                                                   block=args.block, queue=args.queue)
+                                                   block=args.block, queue=args.queue,
+                                                   list_cap=args.list)
         v2 = n_fluid * args.steps / secs2 / 1e6
         # difference between the two precisions after the same steps, by particle id
         def by_id(st):
@@ -249,7 +253,7 @@ def main(argv=None):
                 "v_rel": float(np.abs(a_["v"] - b_["v"]).max() / max(np.abs(a_["v"]).max(), 1e-300)),
                 "x_abs_over_dx": float(np.abs(a_["x"] - b_["x"]).max() / case.dx),
             },
-            "flags": flags2,
+            "flags": int(flags2),
         }
         log(f"{args.compare}: {secs2 * 1e3 / args.steps:.3f} ms/step, {v2:.1f} M updates/s")
         sim2.close()
@@ -275,9 +279,9 @@ def main(argv=None):
                    "precision": args.precision, "n_fluid": n_fluid, "n_wall": case.n_wall,
                    "reorder_every": case.reorder_every if args.reorder_every is None else args.reorder_every,
                    "graph": bool(args.graph), "block_threads": args.block or 256,
-                   "queue_cap": args.queue or 32},
+                   "queue_cap": args.queue or 32, "list_cap": args.list},
         "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
-        "compare": other, "flags": flags,
+        "compare": other, "flags": int(flags),
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -82,7 +82,7 @@ typedef enum {
 /* Sticky device flags returned by sph_poll_errors. */
 #define SPH_FLAG_CLAMPED   1u   /* a particle left the grid; its key was clamped */
 #define SPH_FLAG_NONFINITE 2u   /* a reduction saw a non-finite max|v| or max|a| */
-#define SPH_FLAG_CAPACITY  4u   /* a per-target work list overflowed (handled) */
+#define SPH_FLAG_CAPACITY  4u   /* a neighbour list overflowed (handled, slower) */
 
 typedef struct {
     int32_t n_fluid;         /* fluid particles of this instance (>= 0) */
@@ -113,7 +113,14 @@ typedef struct {
                                 0 = default (32), 16 or 32; -1 = plain direct
                                 search without compaction */
     int32_t use_graph;       /* sph_step_batched replays captured HIP graphs */
-    int32_t reserved[5];
+    int32_t list_cap;        /* neighbour list per target built by the density
+                                sweep and walked by both sweeps: 0 = default
+                                (96 in 3D, 40 in 2D entries), > 0 = capacity,
+                                -1 = no list (both sweeps traverse the stencil).
+                                A target with more neighbours than the capacity
+                                traverses the stencil instead (same results)
+                                and sets SPH_FLAG_CAPACITY. */
+    int32_t reserved[4];
 } sph_params;
 
 typedef struct {

@@ -90,11 +90,14 @@ struct sph_ctx {
     int64_t N = 0, Nw = 0, C = 0;
     int block = 256;
     int qcap = 32;
+    int lcap = 96;
+    bool list_valid = false;  // the neighbour list matches the current sorted order
     bool mixed = false;
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec, o_pos, o_vel, o_rp,
-        o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc;
+        o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
+        o_lcount;
     // state
     bool bound = false, primed = false, cells_built = false;
     sph_buffers buf{};
@@ -202,7 +205,24 @@ void build_layout(sph_ctx *c)
     c->o_inst = take(sizeof(InstDev) * c->idev.size());
     c->o_flags = take(64);
     c->o_clampc = take(sizeof(int) * c->idev.size());
+    c->o_lcount = take(sizeof(int) * nf);
+    c->o_nlist = take(c->lcap > 0 ? sizeof(unsigned) * nf * (size_t)c->lcap : 1);
     c->ws_bytes = off;
+}
+
+// Launch order of chunks: block b (dispatched to XCD b % kXcds) takes the
+// next chunk of the contiguous share of its XCD.  A bijection for any count.
+std::vector<Chunk> xcd_order(const std::vector<Chunk> &chunks)
+{
+    const int n = (int)chunks.size();
+    std::vector<Chunk> out(chunks.size());
+    std::vector<int> offset(kXcds + 1, 0);
+    for (int x = 0; x < kXcds; ++x) {
+        const int count = x < n ? (n - 1 - x) / kXcds + 1 : 0;
+        offset[x + 1] = offset[x] + count;
+    }
+    for (int b = 0; b < n; ++b) out[b] = chunks[offset[b % kXcds] + b / kXcds];
+    return out;
 }
 
 void build_maps(sph_ctx *c)
@@ -218,13 +238,17 @@ void build_maps(sph_ctx *c)
         I.n_wall = c->inst[b].n_wall;
         I.chunk_begin = (int)c->fmap.size();
         for (int64_t s = fo; s < fo + I.n_fluid; s += c->block)
-            c->fmap.push_back({(int)b, (int)s, (int)std::min<int64_t>(s + c->block, fo + I.n_fluid), 0});
+            c->fmap.push_back({(int)b, (int)s, (int)std::min<int64_t>(s + c->block, fo + I.n_fluid),
+                               (int)c->fmap.size()});
         I.chunk_end = (int)c->fmap.size();
         for (int64_t s = wo; s < wo + I.n_wall; s += c->block)
-            c->wmap.push_back({(int)b, (int)s, (int)std::min<int64_t>(s + c->block, wo + I.n_wall), 0});
+            c->wmap.push_back({(int)b, (int)s, (int)std::min<int64_t>(s + c->block, wo + I.n_wall),
+                               (int)c->wmap.size()});
         fo += I.n_fluid;
         wo += I.n_wall;
     }
+    c->fmap = xcd_order(c->fmap);
+    c->wmap = xcd_order(c->wmap);
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -252,6 +276,7 @@ sph_status do_keys(sph_ctx *c, int kick_on, hipStream_t s, bool timed)
 sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
 {
     const Dev &d = c->dev;
+    c->list_valid = false;
     {
         StageTimer t(c, ST_SCAN, s, timed);
         TRY(check_launch(launch_exclusive_scan(d.cnt, d.cell_start, c->C + 1, d.part, 1, s), "cell scan"));
@@ -273,12 +298,18 @@ sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
 sph_status do_density(sph_ctx *c, int use_dt, hipStream_t s, bool timed)
 {
     StageTimer t(c, ST_DENSITY, s, timed);
+    if (c->lcap > 0) {
+        c->list_valid = true;
+        return check_launch(launch_density_list(c->sc, c->dev, c->mixed, use_dt, s), "density");
+    }
     return check_launch(launch_density(c->sc, c->dev, c->mixed, use_dt, s), "density");
 }
 
 sph_status do_force(sph_ctx *c, int fused, hipStream_t s, bool timed)
 {
     StageTimer t(c, ST_FORCE, s, timed);
+    if (c->lcap > 0 && c->list_valid)
+        return check_launch(launch_force_list(c->sc, c->dev, c->mixed, fused, s), "force");
     return check_launch(launch_force(c->sc, c->dev, c->mixed, fused, s), "force");
 }
 
@@ -366,11 +397,15 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     if (block != 64 && block != 128 && block != 256) return fail(SPH_E_ARG, "block_threads must be 0, 64, 128 or 256");
     const int qcap = p->queue_cap == 0 ? 32 : (p->queue_cap < 0 ? 0 : p->queue_cap);
     if (qcap != 0 && qcap != 16 && qcap != 32) return fail(SPH_E_ARG, "queue_cap must be -1, 0, 16 or 32");
+    int lcap = p->list_cap == 0 ? (p->dim == 3 ? 96 : 40) : (p->list_cap < 0 ? 0 : p->list_cap);
+    lcap = (lcap + 3) & ~3;   // stored in quads
+    if (lcap > 4096) return fail(SPH_E_ARG, "list_cap must be at most 4096");
     auto *c = new sph_ctx();
     c->p = *p;
     c->p.inst = nullptr;
     c->block = block;
     c->qcap = qcap;
+    c->lcap = lcap;
     c->mixed = p->precision == SPH_MIXED;
     c->inst.assign(p->inst, p->inst + p->n_instances);
     const double cs = 2.0 * p->h;
@@ -394,7 +429,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     }
     if (N >= INT32_MAX || Nw >= INT32_MAX || C >= INT32_MAX - 1) { delete c; return fail(SPH_E_CAPACITY, "more than 2^31 particles or cells"); }
     if (C + 1 > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many cells for the two-level scan"); }
-    if (qcap > 0 && (N >= (1 << 26) || Nw >= (1 << 26))) { delete c; return fail(SPH_E_CAPACITY, "queued sweeps address at most 2^26 particles per kind; use queue_cap = -1"); }
+    if ((qcap > 0 || lcap > 0) && (N >= (1 << 26) || Nw >= (1 << 26))) { delete c; return fail(SPH_E_CAPACITY, "queued and list sweeps address at most 2^26 particles per kind; use queue_cap = -1 and list_cap = -1"); }
     if ((int64_t)256 * radix_tiles(std::max(N, Nw)) > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many particles for the radix histogram scan"); }
     c->N = N;
     c->Nw = Nw;
@@ -528,6 +563,9 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.nwchunks = (int)c->wmap.size();
     d.block = c->block;
     d.queue_cap = c->qcap;
+    d.list_cap = c->lcap;
+    d.nlist = reinterpret_cast<uint4 *>(ws + c->o_nlist);
+    d.lcount = reinterpret_cast<int *>(ws + c->o_lcount);
     if (!c->fmap.empty())
         HIP_TRY(hipMemcpyAsync(d.fmap, c->fmap.data(), sizeof(Chunk) * c->fmap.size(), hipMemcpyHostToDevice, s));
     if (!c->wmap.empty())
@@ -547,6 +585,7 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     c->bound = true;
     c->primed = false;
     c->cells_built = false;
+    c->list_valid = false;
     c->steps_done = 0;
     return SPH_OK;
 }

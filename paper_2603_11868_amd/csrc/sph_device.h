@@ -31,8 +31,14 @@ struct Chunk {
     int inst;                          // instance of the chunk
     int begin;                         // first particle (global index)
     int end;                           // one past the last
-    int pad;
+    int id;                            // chunk number in particle order (partials slot)
 };
+
+// Workgroups are dispatched to the XCDs round robin (block b runs on XCD
+// b % kXcds).  Chunk maps are laid out so that the blocks of one XCD take
+// consecutive chunks: each XCD then sweeps one contiguous slab of cells and
+// the stencil data shared by neighbouring chunks stays in that XCD's L2.
+constexpr int kXcds = 8;
 
 struct InstDev {
     double lo[3];                      // grid origin

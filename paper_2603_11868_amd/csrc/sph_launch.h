@@ -38,7 +38,10 @@ struct Dev {
     int *clampc;              // [B] clamped keys of the current step
     int nfchunks, nwchunks;
     int block;                // threads per chunk
-    int queue_cap;
+    int queue_cap;            // 0: direct traversal, else LDS hit-queue entries
+    uint4 *nlist;             // [list_cap/4 * N] neighbour list in quads, slot-major
+    int *lcount;              // [N] hits per sorted target (may exceed list_cap)
+    int list_cap;             // 0: sweeps traverse the stencil (no list)
 };
 
 hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s);
@@ -58,6 +61,10 @@ hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t 
 hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s);
 // Force sweep.  fused != 0: also v += dt/2 a and all per-chunk partials.
 hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, hipStream_t s);
+// The same two sweeps on the per-step neighbour list: the density sweep tests
+// the candidates and writes the list, the force sweep only walks it.
+hipError_t launch_density_list(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s);
+hipError_t launch_force_list(const SimConst &sc, const Dev &d, int mixed, int fused, hipStream_t s);
 // Staged half 2: v += dt/2 a (kick_on != 0) and the partials the force sweep
 // does not write.
 hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kick_on);

@@ -22,6 +22,7 @@ import time
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 BLOCKS = (64, 128, 256)
 QUEUES = (-1, 16, 32)
+LISTS = (0, -1)
 REORDERS = (1, 5, 20, 50)
 
 
@@ -30,12 +31,12 @@ def cache_key(arch, dim, precision, n_fluid):
     return f"{arch}/d{dim}/{precision}/n2^{bucket}"
 
 
-def time_variant(case, precision, block, queue, reorder, steps, warmup):
+def time_variant(case, precision, block, queue, reorder, steps, warmup, list_cap=0):
     import torch
     from .sph import Simulation
 
     sim = Simulation(case, precision=precision, block_threads=block, queue_cap=queue,
-                     reorder_every=reorder)
+                     reorder_every=reorder, list_cap=list_cap)
     try:
         sim.prime()
         sim.step(warmup)
@@ -53,18 +54,20 @@ def time_variant(case, precision, block, queue, reorder, steps, warmup):
 
 
 def tune(case, precision="fp64", steps=20, warmup=3, blocks=BLOCKS, queues=QUEUES,
-         reorders=REORDERS, cache_path=DEFAULT_CACHE, log=print):
+         reorders=REORDERS, cache_path=DEFAULT_CACHE, log=print, lists=LISTS):
     """Time every variant; return the fastest as a dict and store it."""
     import torch
 
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     results = []
-    for block, queue, reorder in itertools.product(blocks, queues, reorders):
-        ms, flags = time_variant(case, precision, block, queue, reorder, steps, warmup)
-        results.append({"block_threads": block, "queue_cap": queue, "reorder_every": reorder,
-                        "ms_per_step": round(ms, 5), "flags": flags})
+    for block, lst, queue, reorder in itertools.product(blocks, lists, queues, reorders):
+        if lst >= 0 and queue != queues[0]:
+            continue          # with a list the force sweep has no traversal to queue
+        ms, flags = time_variant(case, precision, block, queue, reorder, steps, warmup, lst)
+        results.append({"block_threads": block, "list_cap": lst, "queue_cap": queue,
+                        "reorder_every": reorder, "ms_per_step": round(ms, 5), "flags": flags})
         if log:
-            log(f"  block {block:3d} queue {queue:3d} K {reorder:3d}: {ms:8.4f} ms/step")
+            log(f"  block {block:3d} list {lst:3d} queue {queue:3d} K {reorder:3d}: {ms:8.4f} ms/step")
     ok = [r for r in results if r["flags"] == 0]
     best = min(ok or results, key=lambda r: r["ms_per_step"])
     key = cache_key(arch, case.dim, precision, case.n_fluid)
@@ -104,12 +107,13 @@ def main(argv=None):
     ap.add_argument("--blocks", default=",".join(map(str, BLOCKS)))
     ap.add_argument("--queues", default=",".join(map(str, QUEUES)))
     ap.add_argument("--reorders", default=",".join(map(str, REORDERS)))
+    ap.add_argument("--lists", default=",".join(map(str, LISTS)))
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     args = ap.parse_args(argv)
     case = dambreak.make_case(args.case)
     ints = lambda s: tuple(int(v) for v in s.split(","))
     e = tune(case, args.precision, args.steps, args.warmup, ints(args.blocks), ints(args.queues),
-             ints(args.reorders), args.cache)
+             ints(args.reorders), args.cache, lists=ints(args.lists))
     print(json.dumps({"case": args.case, "precision": args.precision, "best": e["best"]}))
 
 

@@ -56,7 +56,12 @@ def errors(g, r, x0, rho0=1000.0):
     am = np.abs(r["a"]).max()
     e["a"] = float(np.abs(g["a"] - r["a"]).max() / am)
     dm = np.abs(r["x"] - x0).max()
-    e["x"] = float(np.abs(g["x"] - r["x"]).max() / dm) if dm > 0 else float(np.abs(g["x"] - r["x"]).max())
+    dx = np.abs(g["x"] - r["x"]).max()
+    e["x"] = float(dx / dm) if dm > 0 else float(dx)
+    # the same with the FP64 rounding of the absolute positions taken out:
+    # after one step the displacement is ~1e-8 m while |x| ~ 1 m rounds at ~1e-16
+    slack = 8 * np.finfo(np.float64).eps * np.abs(r["x"]).max()
+    e["x_beyond_rounding"] = float(max(dx - slack, 0.0) / dm) if dm > 0 else float(max(dx - slack, 0.0))
     e["dt"] = float(abs(g["dt"] - r["dt"]) / r["dt"])
     return e
 
