@@ -89,7 +89,7 @@ def candidate_count(sim, h):
 
 def kernel_source_hash():
     hsh = hashlib.sha256()
-    for name in ("sph_kernels.hip", "sph_device.h"):
+    for name in ("sph_sweeps.hip", "sph_step_common.h", "sph_device.h"):
         with open(os.path.join(ROOT, "paper_2603_11868_amd", "csrc", name), "rb") as f:
             hsh.update(f.read())
     return hsh.hexdigest()[:16]
@@ -97,25 +97,31 @@ def kernel_source_hash():
 
 def load_traffic(workload, precision, kernel):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_pmc.json")
+    taken on the current kernel source (else None).  The summary is a text file
+    with `source_hash: ...` and `hbm_bytes_per_launch: ...` lines."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_pmc.md")
     if not os.path.exists(path):
         return None
+    rec = {}
     with open(path) as f:
-        rec = json.load(f)
-    if rec.get("source_hash") != kernel_source_hash():
+        for line in f:
+            m = re.match(r"^\W*(source_hash|hbm_bytes_per_launch)\W*:\s*`?([0-9A-Za-z.+e-]+)", line)
+            if m:
+                rec[m.group(1)] = m.group(2)
+    if rec.get("source_hash") != kernel_source_hash() or "hbm_bytes_per_launch" not in rec:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return float(rec["hbm_bytes_per_launch"])
 
 
-def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0, queue=0,
-            list_cap=0):
+def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
+            list_cap=0, prefetch=0, stage_steps=0):
     import torch
     from paper_2603_11868_amd import sph
 
     sim = sph.Simulation(case, precision=precision, reorder_every=reorder_every,
-                         use_graph=graph, block_threads=block, queue_cap=queue,
-                         list_cap=list_cap)
+                         use_graph=graph, block_threads=block,
+                         list_cap=list_cap, prefetch=prefetch)
     sim.prime()
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -129,6 +135,15 @@ def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, b
     t1 = time.perf_counter()
     stages = sph.sph_stage_times(sim.ctx, reset=True) if timing else {}
     sph.sph_set_timing(sim.ctx, 0)
+    if graph and stage_steps:
+        # graph replays carry no per-stage events: time the stages on eager
+        # launches of the same steps right after the timed region
+        sph.sph_set_timing(sim.ctx, 1)
+        sph.sph_stage_times(sim.ctx, reset=True)
+        sim.step(stage_steps)
+        torch.cuda.synchronize()
+        stages = sph.sph_stage_times(sim.ctx, reset=True)
+        sph.sph_set_timing(sim.ctx, 0)
     flags = sim.poll_errors()
     h = sim.host()
     return sim, h, t1 - t0, stages, flags
@@ -156,8 +171,8 @@ def main(argv=None):
                     help="second precision timed on the same workload")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--queue", type=int, default=0, help="sweep hit-queue capacity (-1: direct)")
     ap.add_argument("--list", type=int, default=0, help="neighbour-list capacity (-1: no list)")
+    ap.add_argument("--prefetch", type=int, default=0, help="candidate records in flight (4 or 8)")
     ap.add_argument("--reorder-every", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps of the CPU sample (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -190,8 +205,10 @@ def main(argv=None):
 
     sim, h, secs, stages, flags = run_gpu(case, args.precision, args.steps, args.warmup,
                                           args.graph, timing=not args.graph,
+                                          stage_steps=min(args.steps, 50),
                                           reorder_every=args.reorder_every, block=args.block,
-                                          queue=args.queue, list_cap=args.list)
+                                          list_cap=args.list,
+                                          prefetch=args.prefetch)
     value = n_fluid * args.steps / secs / 1e6
     log(f"{args.precision}: {secs * 1e3 / args.steps:.3f} ms/step, {value:.1f} M updates/s, flags {flags}")
     for k, (ms, n) in stages.items():
@@ -229,10 +246,11 @@ def main(argv=None):
     other = None
     if args.compare != "none" and args.compare != args.precision:
         sim2, h2, secs2, stages2, flags2 = run_gpu(case, args.compare, args.steps, args.warmup,
-                                                   False, timing=True,
+                                                   args.graph, timing=not args.graph,
+                                                   stage_steps=min(args.steps, 50),
                                                    reorder_every=args.reorder_every,
-                                                   block=args.block, queue=args.queue,
-                                                   list_cap=args.list)
+                                                   block=args.block,
+                                                   list_cap=args.list, prefetch=args.prefetch)
         v2 = n_fluid * args.steps / secs2 / 1e6
         # difference between the two precisions after the same steps, by particle id
         def by_id(st):
@@ -279,7 +297,8 @@ def main(argv=None):
                    "precision": args.precision, "n_fluid": n_fluid, "n_wall": case.n_wall,
                    "reorder_every": case.reorder_every if args.reorder_every is None else args.reorder_every,
                    "graph": bool(args.graph), "block_threads": args.block or 256,
-                   "queue_cap": args.queue or 32, "list_cap": args.list},
+                   "list_cap": args.list,
+                   "prefetch": args.prefetch or 8},
         "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
         "compare": other, "flags": int(flags),
     }

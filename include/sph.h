@@ -109,9 +109,6 @@ typedef struct {
     double g[3];             /* gravity */
     const sph_instance_desc *inst;   /* n_instances entries (copied) */
     int32_t block_threads;   /* threads per sweep block: 0 (default 256), 64, 128, 256 */
-    int32_t queue_cap;       /* per-thread hit queue of the sweeps (LDS entries):
-                                0 = default (32), 16 or 32; -1 = plain direct
-                                search without compaction */
     int32_t use_graph;       /* sph_step_batched replays captured HIP graphs */
     int32_t list_cap;        /* neighbour list per target built by the density
                                 sweep and walked by both sweeps: 0 = default
@@ -119,7 +116,12 @@ typedef struct {
                                 -1 = no list (both sweeps traverse the stencil).
                                 A target with more neighbours than the capacity
                                 traverses the stencil instead (same results)
-                                and sets SPH_FLAG_CAPACITY. */
+                                and sets SPH_FLAG_CAPACITY.  With a list, each
+                                instance set must hold fewer than 2^25 fluid
+                                and 2^25 wall particles (else SPH_E_CAPACITY
+                                from sph_create). */
+    int32_t prefetch;        /* candidate records in flight per thread in the
+                                density sweep: 0 = default (8), 4 or 8 */
     int32_t reserved[4];
 } sph_params;
 

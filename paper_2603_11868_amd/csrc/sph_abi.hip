@@ -89,15 +89,15 @@ struct sph_ctx {
     std::vector<Chunk> fmap, wmap;
     int64_t N = 0, Nw = 0, C = 0;
     int block = 256;
-    int qcap = 32;
     int lcap = 96;
+    int pref = 8;
     bool list_valid = false;  // the neighbour list matches the current sorted order
     bool mixed = false;
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
-    size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec, o_pos, o_vel, o_rp,
+    size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
         o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
-        o_lcount;
+        o_lcount, o_cpos, o_wcpos;
     // state
     bool bound = false, primed = false, cells_built = false;
     sph_buffers buf{};
@@ -168,8 +168,9 @@ void collect_times(sph_ctx *c)
     c->pending.clear();
 }
 
-int rec_pos_bytes(int dim, bool mixed) { return mixed ? (dim == 3 ? 16 : 8) : (dim == 3 ? 32 : 16); }
-int rec_rp_bytes(bool mixed) { return mixed ? 8 : 16; }
+// bytes of one fluid sweep record (two 4-vectors) and of one wall record
+int rec_bytes(bool mixed) { return mixed ? 32 : 64; }
+int wall_rec_bytes(int dim, bool mixed) { return mixed ? (dim == 3 ? 16 : 8) : (dim == 3 ? 32 : 16); }
 
 void build_layout(sph_ctx *c)
 {
@@ -190,13 +191,11 @@ void build_layout(sph_ctx *c)
     c->o_part = take(sizeof(int) * 16384);
     c->o_cnt = take(sizeof(int) * (c->C + 1));
     const size_t nf = (size_t)std::max<int64_t>(c->N, 1);
-    const size_t rec_bytes = align256(nf * rec_pos_bytes(dim, c->mixed)) * 2 + align256(nf * rec_rp_bytes(c->mixed));
+    // the sweep records share their memory with the reorder gather buffer:
+    // the reorder runs before the records are packed
     const size_t scr_bytes = nf * sizeof(double) * (2 * dim + 2);
-    c->o_rec = take(std::max(rec_bytes, scr_bytes));
-    c->o_pos = c->o_rec;
-    c->o_vel = c->o_pos + align256(nf * rec_pos_bytes(dim, c->mixed));
-    c->o_rp = c->o_vel + align256(nf * rec_pos_bytes(dim, c->mixed));
-    c->o_wpos = take((size_t)std::max<int64_t>(c->Nw, 1) * rec_pos_bytes(dim, c->mixed));
+    c->o_rec = take(std::max(nf * rec_bytes(c->mixed), scr_bytes));
+    c->o_wpos = take((size_t)std::max<int64_t>(c->Nw, 1) * wall_rec_bytes(dim, c->mixed));
     c->o_wkey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
     c->o_wskey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
     c->o_partials = take(sizeof(double) * kNPart * std::max<size_t>(c->fmap.size(), 1));
@@ -206,6 +205,10 @@ void build_layout(sph_ctx *c)
     c->o_flags = take(64);
     c->o_clampc = take(sizeof(int) * c->idev.size());
     c->o_lcount = take(sizeof(int) * nf);
+    // FP32 candidate copies (the FP64 path only; the mixed records are FP32)
+    const size_t cbytes = dim == 3 ? 16 : 8;
+    c->o_cpos = take(c->mixed ? 1 : nf * cbytes);
+    c->o_wcpos = take(c->mixed ? 1 : (size_t)std::max<int64_t>(c->Nw, 1) * cbytes);
     c->o_nlist = take(c->lcap > 0 ? sizeof(unsigned) * nf * (size_t)c->lcap : 1);
     c->ws_bytes = off;
 }
@@ -298,19 +301,15 @@ sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
 sph_status do_density(sph_ctx *c, int use_dt, hipStream_t s, bool timed)
 {
     StageTimer t(c, ST_DENSITY, s, timed);
-    if (c->lcap > 0) {
-        c->list_valid = true;
-        return check_launch(launch_density_list(c->sc, c->dev, c->mixed, use_dt, s), "density");
-    }
+    c->list_valid = c->lcap > 0;
     return check_launch(launch_density(c->sc, c->dev, c->mixed, use_dt, s), "density");
 }
 
 sph_status do_force(sph_ctx *c, int fused, hipStream_t s, bool timed)
 {
     StageTimer t(c, ST_FORCE, s, timed);
-    if (c->lcap > 0 && c->list_valid)
-        return check_launch(launch_force_list(c->sc, c->dev, c->mixed, fused, s), "force");
-    return check_launch(launch_force(c->sc, c->dev, c->mixed, fused, s), "force");
+    const int list = c->lcap > 0 && c->list_valid;
+    return check_launch(launch_force(c->sc, c->dev, c->mixed, fused, list, s), "force");
 }
 
 sph_status do_reduce(sph_ctx *c, int prime, hipStream_t s, bool timed)
@@ -395,17 +394,17 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
         return fail(SPH_E_ARG, "alpha >= 0, eps > 0 and positive Courant numbers required");
     const int block = p->block_threads == 0 ? 256 : p->block_threads;
     if (block != 64 && block != 128 && block != 256) return fail(SPH_E_ARG, "block_threads must be 0, 64, 128 or 256");
-    const int qcap = p->queue_cap == 0 ? 32 : (p->queue_cap < 0 ? 0 : p->queue_cap);
-    if (qcap != 0 && qcap != 16 && qcap != 32) return fail(SPH_E_ARG, "queue_cap must be -1, 0, 16 or 32");
     int lcap = p->list_cap == 0 ? (p->dim == 3 ? 96 : 40) : (p->list_cap < 0 ? 0 : p->list_cap);
     lcap = (lcap + 3) & ~3;   // stored in quads
+    const int pref = p->prefetch == 0 ? 8 : p->prefetch;
+    if (pref != 4 && pref != 8) return fail(SPH_E_ARG, "prefetch must be 0, 4 or 8");
     if (lcap > 4096) return fail(SPH_E_ARG, "list_cap must be at most 4096");
     auto *c = new sph_ctx();
     c->p = *p;
     c->p.inst = nullptr;
     c->block = block;
-    c->qcap = qcap;
     c->lcap = lcap;
+    c->pref = pref;
     c->mixed = p->precision == SPH_MIXED;
     c->inst.assign(p->inst, p->inst + p->n_instances);
     const double cs = 2.0 * p->h;
@@ -429,7 +428,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     }
     if (N >= INT32_MAX || Nw >= INT32_MAX || C >= INT32_MAX - 1) { delete c; return fail(SPH_E_CAPACITY, "more than 2^31 particles or cells"); }
     if (C + 1 > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many cells for the two-level scan"); }
-    if ((qcap > 0 || lcap > 0) && (N >= (1 << 26) || Nw >= (1 << 26))) { delete c; return fail(SPH_E_CAPACITY, "queued and list sweeps address at most 2^26 particles per kind; use queue_cap = -1 and list_cap = -1"); }
+    if (lcap > 0 && (N >= (1 << 25) || Nw >= (1 << 25))) { delete c; return fail(SPH_E_CAPACITY, "the neighbour list addresses fewer than 2^25 particles per kind; use list_cap = -1"); }
     if ((int64_t)256 * radix_tiles(std::max(N, Nw)) > scan_max_elems()) { delete c; return fail(SPH_E_CAPACITY, "too many particles for the radix histogram scan"); }
     c->N = N;
     c->Nw = Nw;
@@ -546,11 +545,11 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.hist = reinterpret_cast<int *>(ws + c->o_hist);
     d.part = reinterpret_cast<int *>(ws + c->o_part);
     d.cnt = reinterpret_cast<int *>(ws + c->o_cnt);
-    d.pos = ws + c->o_pos;
-    d.vel = ws + c->o_vel;
-    d.rp = ws + c->o_rp;
+    d.rec = ws + c->o_rec;
     d.scratch = reinterpret_cast<double *>(ws + c->o_rec);
     d.wpos = ws + c->o_wpos;
+    d.cpos = ws + c->o_cpos;
+    d.wcpos = ws + c->o_wcpos;
     d.wkey = reinterpret_cast<int *>(ws + c->o_wkey);
     d.wskey = reinterpret_cast<int *>(ws + c->o_wskey);
     d.partials = reinterpret_cast<double *>(ws + c->o_partials);
@@ -562,8 +561,8 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.nfchunks = (int)c->fmap.size();
     d.nwchunks = (int)c->wmap.size();
     d.block = c->block;
-    d.queue_cap = c->qcap;
     d.list_cap = c->lcap;
+    d.prefetch = c->pref;
     d.nlist = reinterpret_cast<uint4 *>(ws + c->o_nlist);
     d.lcount = reinterpret_cast<int *>(ws + c->o_lcount);
     if (!c->fmap.empty())

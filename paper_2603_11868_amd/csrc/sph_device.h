@@ -5,10 +5,10 @@
 //                  component-major SoA; it is physically reordered by cell
 //                  every K steps, so between reorders it stays nearly sorted;
 //   sorted order   per-step sweep records built right after the sort, one
-//                  aligned record per particle so that a candidate costs one
-//                  or two vector loads: position and velocity (FP64, or FP32
-//                  offsets from the FP64 origin of the particle's cell), and
-//                  the (rho, P) pair written by the density sweep.
+//                  aligned 64-byte (FP64) or 32-byte (FP32) record per
+//                  particle holding position (FP64, or FP32 offset from the
+//                  FP64 origin of the particle's cell), velocity, and the
+//                  (rho, P) pair written by the density sweep.
 // Work is split into chunks of at most one block of consecutive particles of
 // one instance, so every block knows its instance and reductions never mix
 // instances.
@@ -61,12 +61,13 @@ struct SimConst {
     float fg[3], pad2;
 };
 
-// Record types per (dimension, precision).
+// Record types per (dimension, precision): v4 halves of a fluid sweep record,
+// v2 for (rho, P), wpos_t for a wall record.
 template <int DIM, bool MIXED> struct Rec;
-template <> struct Rec<2, false> { using pos_t = dvec2; using vel_t = dvec2; using rp_t = dvec2; using real = double; };
-template <> struct Rec<3, false> { using pos_t = dvec4; using vel_t = dvec4; using rp_t = dvec2; using real = double; };
-template <> struct Rec<2, true>  { using pos_t = fvec2; using vel_t = fvec2; using rp_t = fvec2; using real = float; };
-template <> struct Rec<3, true>  { using pos_t = fvec4; using vel_t = fvec4; using rp_t = fvec2; using real = float; };
+template <> struct Rec<2, false> { using v4 = dvec4; using v2 = dvec2; using wpos_t = dvec2; using real = double; };
+template <> struct Rec<3, false> { using v4 = dvec4; using v2 = dvec2; using wpos_t = dvec4; using real = double; };
+template <> struct Rec<2, true>  { using v4 = fvec4; using v2 = fvec2; using wpos_t = fvec2; using real = float; };
+template <> struct Rec<3, true>  { using v4 = fvec4; using v2 = fvec2; using wpos_t = fvec4; using real = float; };
 
 // ---- wave64 primitives ------------------------------------------------------
 

@@ -16,7 +16,7 @@ hipError_t launch_radix_sort(const int *keys, int64_t n, int64_t ncells, int *sk
                              int *k0, int *v0, int *k1, int *v1, int *hist, int *part,
                              hipStream_t s);
 
-// ---- physics (sph_kernels.hip) ------------------------------------------
+// ---- physics (sph_kernels.hip, sph_sweeps.hip) ----------------------------
 struct Dev {
     // caller buffers
     double *x, *v, *a, *rho;
@@ -27,8 +27,9 @@ struct Dev {
     // workspace
     int *skey, *rk0, *rv0, *rk1, *rv1, *hist, *part;
     int *cnt;                 // [C+1] per-cell counts (zero between steps)
-    void *pos, *vel, *rp;     // sorted sweep records
-    void *wpos;               // sorted wall records
+    void *rec;                // [2N] sorted fluid sweep records (two 4-vectors each)
+    void *wpos;               // [Nw] sorted wall records
+    void *cpos, *wcpos;       // FP32 cell-offset copies for candidate tests (FP64 path)
     int *wkey, *wskey;        // wall keys (storage, sorted)
     double *scratch;          // reorder gather buffer
     double *partials;         // [nchunks * kNPart]
@@ -38,10 +39,10 @@ struct Dev {
     int *clampc;              // [B] clamped keys of the current step
     int nfchunks, nwchunks;
     int block;                // threads per chunk
-    int queue_cap;            // 0: direct traversal, else LDS hit-queue entries
     uint4 *nlist;             // [list_cap/4 * N] neighbour list in quads, slot-major
     int *lcount;              // [N] hits per sorted target (may exceed list_cap)
     int list_cap;             // 0: sweeps traverse the stencil (no list)
+    int prefetch;             // candidate records in flight per thread (4 or 8)
 };
 
 hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s);
@@ -57,14 +58,12 @@ hipError_t launch_wall_pack(const SimConst &sc, const Dev &d, int mixed, hipStre
 hipError_t launch_reorder(const SimConst &sc, const Dev &d, hipStream_t s);
 // Sorted sweep records from the storage-order state.
 hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s);
-// Density sweep.  use_dt = 0 for the prime (dt = 0).
+// Density sweep (sph_sweeps.hip).  use_dt = 0 for the prime (dt = 0).  With
+// list_cap > 0 it also writes the per-step neighbour list.
 hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s);
 // Force sweep.  fused != 0: also v += dt/2 a and all per-chunk partials.
-hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, hipStream_t s);
-// The same two sweeps on the per-step neighbour list: the density sweep tests
-// the candidates and writes the list, the force sweep only walks it.
-hipError_t launch_density_list(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s);
-hipError_t launch_force_list(const SimConst &sc, const Dev &d, int mixed, int fused, hipStream_t s);
+// list != 0: walk the neighbour list written by this step's density sweep.
+hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, int list, hipStream_t s);
 // Staged half 2: v += dt/2 a (kick_on != 0) and the partials the force sweep
 // does not write.
 hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kick_on);

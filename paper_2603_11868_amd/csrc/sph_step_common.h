@@ -1,0 +1,112 @@
+// Device helpers shared by the streaming kernels and the pair sweeps.
+#pragma once
+
+#include "sph_launch.h"
+
+namespace sphx {
+
+// r^2 summed left to right without FMA: the predicate r^2 < (2h)^2 of the FP64
+// path then matches a plain IEEE evaluation bit for bit.
+__device__ __forceinline__ double dist2(double rx, double ry)
+{
+#pragma clang fp contract(off)
+    return rx * rx + ry * ry;
+}
+__device__ __forceinline__ double dist2(double rx, double ry, double rz)
+{
+#pragma clang fp contract(off)
+    return rx * rx + ry * ry + rz * rz;
+}
+__device__ __forceinline__ float dist2(float rx, float ry) { return rx * rx + ry * ry; }
+__device__ __forceinline__ float dist2(float rx, float ry, float rz) { return rx * rx + ry * ry + rz * rz; }
+
+// Half-step kick, rounded like the plain expression (no FMA).
+__device__ __forceinline__ double kick(double v, double a, double dt)
+{
+#pragma clang fp contract(off)
+    return v + 0.5 * dt * a;
+}
+
+// |r| from r^2: correctly rounded in FP64; in FP32 the hardware square root
+// (1 ulp), which the mixed path's tolerance covers.
+__device__ __forceinline__ double root(double r2) { return sqrt(r2); }
+__device__ __forceinline__ float root(float r2) { return __builtin_amdgcn_sqrtf(r2); }
+
+// Wendland C2: W = kW t^4 (2q + 1), F = (1/r) dW/dr = kF t^3, t = 1 - q/2.
+template <class real>
+__device__ __forceinline__ void kernel_WF(real r2, real inv_h, real kW, real kF, real &W, real &F)
+{
+    const real rr = root(r2);
+    const real q = rr * inv_h;
+    const real t = (real)1 - (real)0.5 * q;
+    const real t3 = t * t * t;
+    W = kW * t3 * t * ((real)2 * q + (real)1);
+    F = kF * t3;
+}
+
+template <class real>
+__device__ __forceinline__ void kernel_F(real r2, real inv_h, real kF, real &F)
+{
+    const real rr = root(r2);
+    const real q = rr * inv_h;
+    const real t = (real)1 - (real)0.5 * q;
+    F = kF * t * t * t;
+}
+
+// ---- block partial sums (deterministic: fixed lanes, fixed butterfly, fixed wave order)
+
+// slots: 0 max|v| 1 max|a| 2..4 sum m v 5 kinetic 6 potential 7 internal
+//        8..10 sum m a_ff 11 sum rho 12 pairs 13 non-finite count
+enum { P_VMAX = 0, P_AMAX = 1, P_MOM = 2, P_KE = 5, P_PE = 6, P_IE = 7, P_FF = 8,
+       P_RHO = 11, P_PAIRS = 12, P_BAD = 13 };
+
+__device__ __forceinline__ bool is_max_slot(int s) { return s == P_VMAX || s == P_AMAX; }
+
+// Reduce vals[LO..HI) over the block and write them to out[LO..HI).
+template <int LO, int HI>
+__device__ __forceinline__ void block_partials(double (&vals)[kNPart], double *__restrict__ out)
+{
+    __shared__ double sh[kMaxBlock / 64][kNPart];
+    const int w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int s = LO; s < HI; ++s) {
+        const double r = is_max_slot(s) ? wave_max(vals[s]) : wave_sum(vals[s]);
+        if (lane_id() == 0) sh[w][s] = r;
+    }
+    __syncthreads();
+    const int s = threadIdx.x + LO;
+    if (s < HI) {
+        double r = sh[0][s];
+        for (int q = 1; q < nw; ++q) r = is_max_slot(s) ? fmax(r, sh[q][s]) : r + sh[q][s];
+        out[s] = r;
+    }
+}
+
+// Contributions of one particle to the step diagnostics (FP64).
+template <int DIM>
+__device__ __forceinline__ void state_partials(const SimConst &sc, const InstDev &I, const double *vn,
+                                               const double *an, const double *xi, double rhoi,
+                                               double (&vals)[kNPart])
+{
+    double v2 = 0, a2 = 0, gx = 0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        v2 += vn[c] * vn[c];
+        a2 += an[c] * an[c];
+        gx += sc.g[c] * xi[c];
+        vals[P_MOM + c] = sc.mass * vn[c];
+    }
+    const double vm = sqrt(v2), am = sqrt(a2);
+    vals[P_VMAX] = vm;
+    vals[P_AMAX] = am;
+    vals[P_KE] = 0.5 * sc.mass * v2;
+    vals[P_PE] = -sc.mass * gx;
+    vals[P_IE] = rhoi > sc.rho0
+                     ? sc.mass * I.c0 * I.c0 * (log(rhoi / sc.rho0) + sc.rho0 / rhoi - 1.0)
+                     : 0.0;
+    vals[P_RHO] = rhoi;
+    vals[P_BAD] = (isfinite(vm) && isfinite(am)) ? 0.0 : 1.0;
+}
+
+}  // namespace sphx

@@ -1,0 +1,901 @@
+// Pair sweeps of libsph: sorted sweep records, neighbour traversal (direct
+// search over the 3^d nearest cells, Sec. 5 of the paper), the per-step
+// neighbour list, and the density and force sweeps.
+//
+// Fluid sweep record, two 4-vectors per particle, rec[2k] = A, rec[2k+1] = B:
+//   3D  A = (x, y, z, vx)   B = (vy, vz, rho, P)
+//   2D  A = (x, y, vx, vy)  B = (rho, P, -, -)
+// x is the FP64 position on the FP64 path and the FP32 offset from the FP64
+// origin of the particle's cell on the mixed path.  k_pack writes A and the
+// velocity half of B; the density sweep writes (rho, P).  One particle's data
+// for the force sweep is one 64-byte (FP64) or 32-byte (FP32) block.
+// Walls: wpos (FP64 position, or FP32 cell offset).  The FP64 path also keeps
+// FP32 cell-offset copies (cpos, wcpos) for cheap candidate tests.
+#include "sph_step_common.h"
+
+namespace sphx {
+
+// Neighbour-list entries, 32 bits: source slot in bits 0..24; on the mixed path
+// the source cell's offset from the target cell in bits 25..30 (two bits per
+// axis, offset + 1); wall flag in bit 31.
+constexpr int kSlotBits = 25;
+constexpr unsigned kSlotMask = (1u << kSlotBits) - 1u;
+constexpr unsigned kWallBit = 0x80000000u;
+
+__device__ __forceinline__ unsigned offset_bits(int ox, int oy, int oz)
+{
+    return (unsigned)((ox + 1) | ((oy + 1) << 2) | ((oz + 1) << 4)) << kSlotBits;
+}
+
+// Element s of an array addressed with a 32-bit byte offset (list sweeps only:
+// they handle fewer than 2^25 particles per kind, so s * sizeof(T) < 2^32).
+template <class T>
+__device__ __forceinline__ T ld32(const T *__restrict__ base, int s)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                        (uint32_t)s * (uint32_t)sizeof(T));
+}
+
+template <int DIM> struct Cand;
+template <> struct Cand<2> { using t = fvec2; };
+template <> struct Cand<3> { using t = fvec4; };
+
+// Record access for one (dimension, precision).
+template <int DIM, bool MIXED>
+struct RV {
+    using R = Rec<DIM, MIXED>;
+    using real = typename R::real;
+    using v4 = typename R::v4;
+    using v2 = typename R::v2;
+    using wpos_t = typename R::wpos_t;
+
+    __device__ __forceinline__ static void pos(const v4 &A, real *p)
+    {
+        p[0] = A.x;
+        p[1] = A.y;
+        if constexpr (DIM == 3) p[2] = A.z;
+        else p[2] = 0;
+    }
+    __device__ __forceinline__ static void wall_pos(const wpos_t &w, real *p)
+    {
+        p[0] = w.x;
+        p[1] = w.y;
+        if constexpr (DIM == 3) p[2] = w.z;
+        else p[2] = 0;
+    }
+    // velocity from A and the first half of B
+    __device__ __forceinline__ static void vel(const v4 &A, const v4 &B, real *v)
+    {
+        if constexpr (DIM == 3) {
+            v[0] = A.w;
+            v[1] = B.x;
+            v[2] = B.y;
+        } else {
+            v[0] = A.z;
+            v[1] = A.w;
+            v[2] = 0;
+        }
+    }
+    __device__ __forceinline__ static real rho(const v4 &B) { if constexpr (DIM == 3) return B.z; else return B.x; }
+    __device__ __forceinline__ static real P(const v4 &B) { if constexpr (DIM == 3) return B.w; else return B.y; }
+    // the v2 slot of B that holds (rho, P), counted in v2 units from rec
+    __device__ __forceinline__ static int64_t rhoP_slot(int k) { return 4 * (int64_t)k + (DIM == 3 ? 3 : 2); }
+    // loads of A, the velocity half of B (3D), the whole B
+    __device__ __forceinline__ static v4 loadA(const v4 *__restrict__ rec, int s) { return rec[2 * (int64_t)s]; }
+    __device__ __forceinline__ static v4 loadB(const v4 *__restrict__ rec, int s)
+    {
+        if constexpr (DIM == 3) {
+            return rec[2 * (int64_t)s + 1];
+        } else {
+            const v2 h = reinterpret_cast<const v2 *>(rec)[4 * (int64_t)s + 2];
+            v4 B{};
+            B.x = h.x;
+            B.y = h.y;
+            return B;
+        }
+    }
+    __device__ __forceinline__ static v4 loadBv(const v4 *__restrict__ rec, int s)
+    {
+        v4 B{};
+        if constexpr (DIM == 3) {
+            const v2 h = reinterpret_cast<const v2 *>(rec)[4 * (int64_t)s + 2];
+            B.x = h.x;
+            B.y = h.y;
+        }
+        (void)rec;
+        (void)s;
+        return B;
+    }
+};
+
+// How much of B a sweep needs from each fluid source.
+enum { NEED_NONE = 0, NEED_VEL = 1, NEED_ALL = 2 };
+
+template <int DIM, bool MIXED, int NEED>
+__device__ __forceinline__ typename RV<DIM, MIXED>::v4 load_need(const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
+                                                                 int s)
+{
+    using V = RV<DIM, MIXED>;
+    if constexpr (NEED == NEED_ALL) return V::loadB(rec, s);
+    else if constexpr (NEED == NEED_VEL) return V::loadBv(rec, s);
+    else return typename V::v4{};
+}
+
+// Pair vector r = t - x_j, where t is the target position seen from the
+// source's cell.  FP64: positions are absolute and t = x_i.  FP32: offsets from
+// the cell origins, and t = o_i - (c_j - c_i) cs with c_j - c_i in {-1, 0, 1}
+// per axis; that product is exact, so t is one rounding of the difference
+// whether or not the compiler fuses it.
+template <int DIM, bool MIXED, class real>
+__device__ __forceinline__ void shift_target(const real *pi, int ox, int oy, int oz, real cs, real *t)
+{
+    if constexpr (MIXED) {
+        t[0] = pi[0] - (real)ox * cs;
+        t[1] = pi[1] - (real)oy * cs;
+        t[2] = DIM == 3 ? pi[2] - (real)oz * cs : (real)0;
+    } else {
+        (void)ox; (void)oy; (void)oz; (void)cs;
+        t[0] = pi[0];
+        t[1] = pi[1];
+        t[2] = pi[2];
+    }
+}
+
+template <int DIM, class real>
+__device__ __forceinline__ void sub_vec(const real *t, const real *pj, real *r)
+{
+    r[0] = t[0] - pj[0];
+    r[1] = t[1] - pj[1];
+    r[2] = DIM == 3 ? t[2] - pj[2] : (real)0;
+}
+
+// Shifted targets of one stencil row: the row spans cells xlo..xhi (at most
+// three), and a source slot s lies in cell xlo + (s >= b1) + (s >= b2).
+template <int DIM, bool SHIFT, class real>
+struct RowTarget {
+    real x, cs, ty, tz;
+    int b1, b2, ox0, oy, oz;
+    __device__ __forceinline__ void init(const real *pi, int ox, int dy, int dz, real cs_, int b1_, int b2_)
+    {
+        b1 = b1_;
+        b2 = b2_;
+        ox0 = ox;
+        oy = dy;
+        oz = dz;
+        cs = cs_;
+        x = pi[0];
+        real t[3];
+        shift_target<DIM, SHIFT>(pi, ox, dy, dz, cs, t);
+        ty = t[1];
+        tz = t[2];
+    }
+    __device__ __forceinline__ int ox(int s) const { return ox0 + (s >= b1) + (s >= b2); }
+    __device__ __forceinline__ void at(int s, real *t) const
+    {
+        if constexpr (SHIFT) t[0] = x - (real)ox(s) * cs;
+        else t[0] = x;
+        t[1] = ty;
+        t[2] = tz;
+    }
+    // list-entry offset bits of slot s
+    __device__ __forceinline__ unsigned bits(int s) const { return offset_bits(ox(s), oy, oz); }
+};
+
+template <int DIM, class real>
+__device__ __forceinline__ real norm2(const real *r)
+{
+    if constexpr (DIM == 3) return dist2(r[0], r[1], r[2]);
+    else return dist2(r[0], r[1]);
+}
+
+// ---------------------------------------------------------------------------
+// sweep records
+// ---------------------------------------------------------------------------
+
+// Cell-relative FP32 offsets of a position (the FP64 origin lo + c cs).
+template <int DIM>
+__device__ __forceinline__ void cell_offset_f32(const double *xi, const InstDev &I, int lk, double cs, float *o)
+{
+    const int cx = lk % I.ncell[0];
+    const int t = lk / I.ncell[0];
+    const int cy = t % I.ncell[1];
+    const int cz = t / I.ncell[1];
+    o[0] = (float)(xi[0] - (I.lo[0] + cx * cs));
+    o[1] = (float)(xi[1] - (I.lo[1] + cy * cs));
+    o[2] = DIM == 3 ? (float)(xi[2] - (I.lo[2] + cz * cs)) : 0.0f;
+}
+
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(kMaxBlock) void k_pack(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const double *__restrict__ x, const double *__restrict__ v, const int *__restrict__ perm,
+    const int *__restrict__ skey, int n, typename Rec<DIM, MIXED>::v4 *__restrict__ rec,
+    typename Cand<DIM>::t *__restrict__ cpos)
+{
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const InstDev &I = inst[ch.inst];
+    const int i = perm[k];
+    const int lk = skey[k] - I.cell_base;
+    double xi[3] = {0, 0, 0}, vi[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        xi[c] = x[(int64_t)c * n + i];
+        vi[c] = v[(int64_t)c * n + i];
+    }
+    float o[3];
+    cell_offset_f32<DIM>(xi, I, lk, sc.cs, o);
+    real p[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[c] = MIXED ? (real)o[c] : (real)xi[c];
+    typename V::v4 A;
+    if constexpr (DIM == 3) {
+        A.x = p[0]; A.y = p[1]; A.z = p[2]; A.w = (real)vi[0];
+        typename V::v2 Bv;
+        Bv.x = (real)vi[1];
+        Bv.y = (real)vi[2];
+        reinterpret_cast<typename V::v2 *>(rec)[4 * (int64_t)k + 2] = Bv;
+    } else {
+        A.x = p[0]; A.y = p[1]; A.z = (real)vi[0]; A.w = (real)vi[1];
+    }
+    rec[2 * (int64_t)k] = A;
+    if constexpr (!MIXED) {
+        typename Cand<DIM>::t cp;
+        cp.x = o[0];
+        cp.y = o[1];
+        if constexpr (DIM == 3) { cp.z = o[2]; cp.w = 0.0f; }
+        cpos[k] = cp;
+    }
+}
+
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(kMaxBlock) void k_wall_pack(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const double *__restrict__ xw, const int *__restrict__ wperm, const int *__restrict__ wskey,
+    int nw, typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos, typename Cand<DIM>::t *__restrict__ wcpos)
+{
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const InstDev &I = inst[ch.inst];
+    const int j = wperm[k];
+    double xj[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) xj[c] = xw[(int64_t)c * nw + j];
+    float o[3];
+    cell_offset_f32<DIM>(xj, I, wskey[k] - I.cell_base, sc.cs, o);
+    typename V::wpos_t w;
+    w.x = MIXED ? (real)o[0] : (real)xj[0];
+    w.y = MIXED ? (real)o[1] : (real)xj[1];
+    if constexpr (DIM == 3) {
+        w.z = MIXED ? (real)o[2] : (real)xj[2];
+        w.w = 0;
+    }
+    wpos[k] = w;
+    if constexpr (!MIXED) {
+        typename Cand<DIM>::t cp;
+        cp.x = o[0];
+        cp.y = o[1];
+        if constexpr (DIM == 3) { cp.z = o[2]; cp.w = 0.0f; }
+        wcpos[k] = cp;
+    }
+}
+
+template <int DIM, bool MIXED>
+static void pack_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    k_pack<DIM, MIXED><<<d.nfchunks, d.block, 0, s>>>(
+        sc, d.fmap, d.inst, d.x, d.v, d.perm, d.skey, sc.N,
+        static_cast<typename Rec<DIM, MIXED>::v4 *>(d.rec), static_cast<typename Cand<DIM>::t *>(d.cpos));
+}
+
+hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) pack_dispatch<2, true>(sc, d, s); else pack_dispatch<2, false>(sc, d, s); }
+    else { if (mixed) pack_dispatch<3, true>(sc, d, s); else pack_dispatch<3, false>(sc, d, s); }
+    return hipGetLastError();
+}
+
+template <int DIM, bool MIXED>
+static void wall_pack_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    k_wall_pack<DIM, MIXED><<<d.nwchunks, d.block, 0, s>>>(
+        sc, d.wmap, d.inst, d.xw, d.wall_perm, d.wskey, sc.Nw,
+        static_cast<typename Rec<DIM, MIXED>::wpos_t *>(d.wpos), static_cast<typename Cand<DIM>::t *>(d.wcpos));
+}
+
+hipError_t launch_wall_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
+{
+    if (d.nwchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) wall_pack_dispatch<2, true>(sc, d, s); else wall_pack_dispatch<2, false>(sc, d, s); }
+    else { if (mixed) wall_pack_dispatch<3, true>(sc, d, s); else wall_pack_dispatch<3, false>(sc, d, s); }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stencil geometry
+// ---------------------------------------------------------------------------
+
+struct CellPos {
+    int cx, cy, cz;
+};
+
+__device__ __forceinline__ CellPos decode_cell(const InstDev &I, int lk)
+{
+    CellPos c;
+    c.cx = lk % I.ncell[0];
+    const int t = lk / I.ncell[0];
+    c.cy = t % I.ncell[1];
+    c.cz = t / I.ncell[1];
+    return c;
+}
+
+// Offsets of a target inside its own cell, per axis (in [0, cs) up to rounding).
+template <int DIM, bool MIXED>
+__device__ __forceinline__ void target_offsets(const SimConst &sc, const InstDev &I, const CellPos &c,
+                                               const typename RV<DIM, MIXED>::real *pi,
+                                               typename RV<DIM, MIXED>::real *o)
+{
+    if constexpr (MIXED) {
+        o[0] = pi[0];
+        o[1] = pi[1];
+        o[2] = pi[2];
+    } else {
+        o[0] = pi[0] - (I.lo[0] + c.cx * sc.cs);
+        o[1] = pi[1] - (I.lo[1] + c.cy * sc.cs);
+        o[2] = DIM == 3 ? pi[2] - (I.lo[2] + c.cz * sc.cs) : 0.0;
+    }
+}
+
+// Stencil row (dy, dz) of a target with in-cell offsets o: false when every
+// point of the row is at least 2h away, else the x range of cells that can
+// hold a neighbour.  cut2m is (2h)^2 enlarged by a margin far above the
+// rounding of o, so a skipped cell never holds a particle that passes the
+// r^2 < (2h)^2 predicate: the neighbour set is unchanged.
+template <class real>
+__device__ __forceinline__ bool row_cells(const real *o, real cs, real cut2m, int dy, int dz, int cx,
+                                          int ncx, int &xlo, int &xhi)
+{
+    real d2 = 0;
+    if (dy < 0) d2 += o[1] * o[1];
+    else if (dy > 0) { const real t = cs - o[1]; d2 += t * t; }
+    if (dz < 0) d2 += o[2] * o[2];
+    else if (dz > 0) { const real t = cs - o[2]; d2 += t * t; }
+    if (d2 >= cut2m) return false;
+    xlo = (cx > 0 && o[0] * o[0] + d2 < cut2m) ? cx - 1 : cx;
+    const real t = cs - o[0];
+    xhi = (cx < ncx - 1 && t * t + d2 < cut2m) ? cx + 1 : cx;
+    return true;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ auto cull_margin(const SimConst &sc)
+{
+    if constexpr (MIXED) return sc.fcut2 * (float)(1.0 + 1e-5);
+    else return sc.cut2 * (1.0 + 1e-9);
+}
+
+// ---------------------------------------------------------------------------
+// direct search: fn(wall, s, r, r2, A_j, B_j) for every neighbour of target k,
+// fluid slots of a stencil row first, then its wall slots; rows in z, y order
+// ---------------------------------------------------------------------------
+
+template <int DIM, bool MIXED, int NEED, class Fn>
+__device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev &I, int lk, int k,
+                                               const typename RV<DIM, MIXED>::real *pi,
+                                               const int *__restrict__ cstart, const int *__restrict__ wstart,
+                                               const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
+                                               const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
+                                               Fn &&fn)
+{
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    using v4 = typename V::v4;
+    const CellPos c = decode_cell(I, lk);
+    const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
+    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
+    const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
+    const real cut2m = cull_margin<MIXED>(sc);
+    real o[3];
+    target_offsets<DIM, MIXED>(sc, I, c, pi, o);
+    const int dz_lo = (DIM == 3 && c.cz > 0) ? -1 : 0;
+    const int dz_hi = (DIM == 3 && c.cz < ncz - 1) ? 1 : 0;
+    for (int dz = dz_lo; dz <= dz_hi; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = c.cy + dy;
+            if (yy < 0 || yy >= ncy) continue;
+            int xlo, xhi;
+            if (!row_cells(o, cs, cut2m, dy, dz, c.cx, ncx, xlo, xhi)) continue;
+            const int row = I.cell_base + (yy + ncy * (c.cz + dz)) * ncx;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int *__restrict__ st = pass == 0 ? cstart : wstart;
+                const int s0 = st[row + xlo], s1 = st[row + xhi + 1];
+                // cell boundaries inside the row matter only for the FP32 offsets
+                const int b1 = MIXED && xlo + 1 <= xhi ? st[row + xlo + 1] : s1;
+                const int b2 = MIXED && xlo + 2 <= xhi ? st[row + xlo + 2] : s1;
+                RowTarget<DIM, MIXED, real> rt;
+                rt.init(pi, xlo - c.cx, dy, dz, cs, b1, b2);
+                for (int s = s0; s < s1; ++s) {
+                    if (pass == 0 && s == k) continue;
+                    v4 A{};
+                    real pj[3], t[3], r[3];
+                    if (pass == 0) {
+                        A = V::loadA(rec, s);
+                        V::pos(A, pj);
+                    } else {
+                        V::wall_pos(wpos[s], pj);
+                    }
+                    rt.at(s, t);
+                    sub_vec<DIM>(t, pj, r);
+                    const real r2 = norm2<DIM>(r);
+                    if (r2 < cut2) {
+                        if (pass == 0) fn(false, s, r, r2, A, load_need<DIM, MIXED, NEED>(rec, s));
+                        else fn(true, s, r, r2, v4{}, v4{});
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// neighbour list
+//
+// The density sweep tests the candidates once and writes each target's hits to
+// a slot-major list of 16-byte quads, quad q of target k at nlist[q * N + k];
+// its own pair loop and the whole force sweep then walk that list: the force
+// sweep tests no candidates, and a wave reads 1 KiB contiguous per quad.  A
+// target with more than `cap` neighbours walks the stencil instead (same
+// neighbours, same order) and raises SPH_FLAG_CAPACITY.
+// ---------------------------------------------------------------------------
+
+// Phase 1: candidate tests of target k, hits appended to its list.  Returns the
+// number of hits (possibly above cap; only the first cap are stored).
+//
+// Candidates are read as FP32 cell offsets (the A vectors on the mixed path,
+// the cpos copies on the FP64 path), U per lane in flight, with the index
+// clamped instead of branched.  The mixed path decides with the FP32 r^2.  The
+// FP64 path decides in FP32 except inside a band of relative width 1e-4 around
+// (2h)^2 -- the FP32 r^2 of a pair near the cutoff is within ~3e-6 of the exact
+// one -- and recomputes r^2 in FP64 there, so its neighbour set is the exact
+// FP64 one.  A target far outside its cell (a clamped particle) takes the FP64
+// test for every candidate.  Hits enter a four-entry shift register that is
+// stored as one quad whenever it fills.
+template <int DIM, bool MIXED, int U>
+__device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, int lk, int k,
+                                          const typename RV<DIM, MIXED>::real *pi, const float *ci,
+                                          const int *__restrict__ cstart, const int *__restrict__ wstart,
+                                          const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
+                                          const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
+                                          const typename Cand<DIM>::t *__restrict__ cpos,
+                                          const typename Cand<DIM>::t *__restrict__ wcpos,
+                                          uint4 *__restrict__ nlist, int cap, int n)
+{
+    using V = RV<DIM, MIXED>;
+    using VF = RV<DIM, true>;
+    using real = typename V::real;
+    const CellPos c = decode_cell(I, lk);
+    const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
+    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
+    const real cut2m = cull_margin<MIXED>(sc);
+    const float fcs = sc.fcs, fcut2 = sc.fcut2;
+    real o[3];
+    target_offsets<DIM, MIXED>(sc, I, c, pi, o);
+    float lo = fcut2 * (1.0f - 1e-4f), hi = fcut2 * (1.0f + 1e-4f);
+    if constexpr (!MIXED) {
+        bool far = false;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) far |= fabs((double)o[a]) > 4.0 * sc.cs;
+        if (far) { lo = -1.0f; hi = __builtin_huge_valf(); }
+    }
+    int m = 0;
+    uint4 buf = make_uint4(0u, 0u, 0u, 0u);
+    const int dz_lo = (DIM == 3 && c.cz > 0) ? -1 : 0;
+    const int dz_hi = (DIM == 3 && c.cz < ncz - 1) ? 1 : 0;
+    for (int dz = dz_lo; dz <= dz_hi; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = c.cy + dy;
+            if (yy < 0 || yy >= ncy) continue;
+            int xlo, xhi;
+            if (!row_cells(o, cs, cut2m, dy, dz, c.cx, ncx, xlo, xhi)) continue;
+            const int row = I.cell_base + (yy + ncy * (c.cz + dz)) * ncx;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int *__restrict__ st = pass == 0 ? cstart : wstart;
+                const unsigned wall_bit = pass == 1 ? kWallBit : 0u;
+                const int s0 = st[row + xlo];
+                const int s1 = st[row + xhi + 1];
+                const int b1 = xlo + 1 <= xhi ? st[row + xlo + 1] : s1;
+                const int b2 = xlo + 2 <= xhi ? st[row + xlo + 2] : s1;
+                RowTarget<DIM, true, float> rf;      // FP32 candidate test
+                rf.init(ci, xlo - c.cx, dy, dz, fcs, b1, b2);
+                for (int t0 = s0; t0 < s1; t0 += U) {
+                    float cj[U][3];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int s = min(t0 + u, s1 - 1);
+                        if constexpr (MIXED) {
+                            if (pass == 0) {
+                                const typename VF::v4 A = ld32(rec, 2 * s);
+                                cj[u][0] = A.x; cj[u][1] = A.y; cj[u][2] = DIM == 3 ? A.z : 0.0f;
+                            } else {
+                                VF::wall_pos(ld32(wpos, s), cj[u]);
+                            }
+                        } else {
+                            const typename Cand<DIM>::t w = pass == 0 ? ld32(cpos, s) : ld32(wcpos, s);
+                            cj[u][0] = w.x;
+                            cj[u][1] = w.y;
+                            if constexpr (DIM == 3) cj[u][2] = w.z;
+                            else cj[u][2] = 0.0f;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int s = t0 + u;
+                        float t[3], r[3];
+                        rf.at(s, t);
+                        sub_vec<DIM>(t, cj[u], r);
+                        const float r2f = norm2<DIM>(r);
+                        bool hit = s < s1 && !(pass == 0 && s == k);
+                        if constexpr (MIXED) {
+                            hit = hit && r2f < fcut2;
+                        } else {
+                            hit = hit && r2f < hi;
+                            if (hit && !(r2f < lo)) {
+                                real pj[3], rr[3];
+                                if (pass == 0) V::pos(V::loadA(rec, s), pj);
+                                else V::wall_pos(wpos[s], pj);
+                                sub_vec<DIM>(pi, pj, rr);
+                                hit = norm2<DIM>(rr) < (real)sc.cut2;
+                            }
+                        }
+                        if (hit) {
+                            unsigned e = wall_bit | (unsigned)s;
+                            if constexpr (MIXED) e |= rf.bits(s);
+                            buf.x = buf.y;
+                            buf.y = buf.z;
+                            buf.z = buf.w;
+                            buf.w = e;
+                            ++m;
+                            if ((m & 3) == 0 && m <= cap) nlist[(int64_t)((m >> 2) - 1) * n + k] = buf;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // the last partial quad: its entries sit in the top (m & 3) words
+    const int rest = m & 3;
+    if (rest != 0 && m <= cap) {
+        uint4 q;
+        q.x = rest == 1 ? buf.w : (rest == 2 ? buf.z : buf.y);
+        q.y = rest == 2 ? buf.w : buf.z;
+        q.z = buf.w;
+        q.w = 0u;
+        nlist[(int64_t)(m >> 2) * n + k] = q;
+    }
+    return m;
+}
+
+// Phase 2: fn(wall, s, r, r2, A_j, B_j) for the first m (<= cap) entries of
+// target k; the records of U entries are fetched before any of them is used.
+template <int DIM, bool MIXED, int U, int NEED, class Fn>
+__device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
+                                          const typename RV<DIM, MIXED>::real *pi,
+                                          const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
+                                          const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
+                                          const uint4 *__restrict__ nlist, int n, Fn &&fn)
+{
+    static_assert(U == 1 || U == 2 || U == 4, "entries come in quads");
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    using v4 = typename V::v4;
+    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
+    for (int q0 = 0; q0 < m; q0 += 4) {
+        const uint4 quad = nlist[(int64_t)(q0 >> 2) * n + k];
+        const unsigned eq[4] = {quad.x, quad.y, quad.z, quad.w};
+#pragma unroll
+        for (int h = 0; h < 4; h += U) {
+            v4 A[U], B[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (q0 + h + u < m) {
+                    const unsigned e = eq[h + u];
+                    const int s = (int)(e & kSlotMask);
+                    if (e & kWallBit) {             // position only, zero velocity
+                        const typename V::wpos_t w = ld32(wpos, s);
+                        A[u] = v4{};
+                        A[u].x = w.x;
+                        A[u].y = w.y;
+                        if constexpr (DIM == 3) A[u].z = w.z;
+                        B[u] = v4{};
+                    } else {
+                        A[u] = ld32(rec, 2 * s);
+                        if constexpr (NEED == NEED_ALL && DIM == 3) B[u] = ld32(rec, 2 * s + 1);
+                        else B[u] = load_need<DIM, MIXED, NEED>(rec, s);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (q0 + h + u < m) {
+                    const unsigned e = eq[h + u];
+                    real pj[3], t[3], r[3];
+                    V::pos(A[u], pj);
+                    if constexpr (MIXED) {
+                        const int ox = (int)((e >> kSlotBits) & 3u) - 1;
+                        const int oy = (int)((e >> (kSlotBits + 2)) & 3u) - 1;
+                        const int oz = (int)((e >> (kSlotBits + 4)) & 3u) - 1;
+                        shift_target<DIM, true>(pi, ox, oy, oz, cs, t);
+                    } else {
+                        shift_target<DIM, false>(pi, 0, 0, 0, cs, t);
+                    }
+                    sub_vec<DIM>(t, pj, r);
+                    fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, norm2<DIM>(r), A[u], B[u]);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// density sweep
+// ---------------------------------------------------------------------------
+
+// LIST = 0: direct search.  LIST = 1: build the list, then walk it.
+template <int DIM, bool MIXED, int LIST, int PF>
+__global__ __launch_bounds__(kMaxBlock) void k_density(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
+    const int *__restrict__ wstart, typename Rec<DIM, MIXED>::v4 *__restrict__ rec,
+    const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos, const typename Cand<DIM>::t *__restrict__ cpos,
+    const typename Cand<DIM>::t *__restrict__ wcpos, double *__restrict__ rho, int *__restrict__ count,
+    const double *__restrict__ dt, int use_dt, uint4 *__restrict__ nlist, int *__restrict__ lcount, int cap,
+    unsigned *__restrict__ flags)
+{
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    using v4 = typename V::v4;
+    constexpr int NEED = DIM == 3 ? NEED_VEL : NEED_NONE;
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const int n = sc.N;
+    const InstDev &I = inst[ch.inst];
+    const int lk = skey[k] - I.cell_base;
+    const v4 Ai = V::loadA(rec, k);
+    const v4 Bi = load_need<DIM, MIXED, NEED>(rec, k);
+    real pi[3], vi[3];
+    V::pos(Ai, pi);
+    V::vel(Ai, Bi, vi);
+    const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
+    const real kW = MIXED ? (real)sc.fkW : (real)sc.kW;
+    const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
+    real sigma = MIXED ? (real)0 : (real)sc.W0;
+    real drho = 0;
+    int cnt = 0;
+    auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj)
+        __attribute__((always_inline)) {
+        (void)wall;                        // wall records carry zero velocity
+        real W, F;
+        kernel_WF(r2, inv_h, kW, kF, W, F);
+        real vj[3];
+        V::vel(Aj, Bj, vj);
+        real vr = (vi[0] - vj[0]) * r[0] + (vi[1] - vj[1]) * r[1];
+        if constexpr (DIM == 3) vr += (vi[2] - vj[2]) * r[2];
+        sigma += W;
+        drho += vr * F;
+        ++cnt;
+    };
+    if constexpr (LIST) {
+        float ci[3];
+        if constexpr (MIXED) {
+            ci[0] = pi[0]; ci[1] = pi[1]; ci[2] = pi[2];
+        } else {
+            const typename Cand<DIM>::t cp = cpos[k];
+            ci[0] = cp.x; ci[1] = cp.y;
+            if constexpr (DIM == 3) ci[2] = cp.z;
+            else ci[2] = 0.0f;
+        }
+        const int m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+                                                 nlist, cap, n);
+        if (m <= cap) {
+            walk_list<DIM, MIXED, 4, NEED>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+        } else {
+            atomicOr(flags, 4u);
+            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        }
+        lcount[k] = m;
+    } else {
+        for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+    }
+    const int i = perm[k];
+    const double sig = MIXED ? sc.W0 + (double)sigma : (double)sigma;
+    const double rho_sum = sc.mass * sig;
+    const double dtb = use_dt ? dt[ch.inst] : 0.0;
+    const double rho_star = rho[i] + dtb * (sc.mass * (double)drho);
+    const double excess = rho_star - rho_sum;
+    const double rn = excess > 0.0 ? rho_sum + excess * sc.rho0 / rho_star : rho_sum;
+    double p = I.c0 * I.c0 * (rn - sc.rho0);
+    if (p < 0.0) p = 0.0;
+    const double P = p / (rn * rn);
+    rho[i] = rn;
+    count[i] = cnt;
+    typename V::v2 out;
+    out.x = (real)rn;
+    out.y = (real)P;
+    reinterpret_cast<typename V::v2 *>(rec)[V::rhoP_slot(k)] = out;
+}
+
+template <int DIM, bool MIXED, int LIST, int PF>
+static void density_dispatch(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
+{
+    using R = Rec<DIM, MIXED>;
+    k_density<DIM, MIXED, LIST, PF><<<d.nfchunks, d.block, 0, s>>>(
+        sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, static_cast<typename R::v4 *>(d.rec),
+        static_cast<const typename R::wpos_t *>(d.wpos), static_cast<const typename Cand<DIM>::t *>(d.cpos),
+        static_cast<const typename Cand<DIM>::t *>(d.wcpos), d.rho, d.count, d.dt, use_dt, d.nlist, d.lcount,
+        d.list_cap, d.flags);
+}
+
+template <int DIM, bool MIXED>
+static void density_variant(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
+{
+    if (d.list_cap <= 0) density_dispatch<DIM, MIXED, 0, 4>(sc, d, use_dt, s);
+    else if (d.prefetch == 4) density_dispatch<DIM, MIXED, 1, 4>(sc, d, use_dt, s);
+    else density_dispatch<DIM, MIXED, 1, 8>(sc, d, use_dt, s);
+}
+
+hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) density_variant<2, true>(sc, d, use_dt, s); else density_variant<2, false>(sc, d, use_dt, s); }
+    else { if (mixed) density_variant<3, true>(sc, d, use_dt, s); else density_variant<3, false>(sc, d, use_dt, s); }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// force sweep (+ half 2 and all partials when fused)
+// ---------------------------------------------------------------------------
+
+// LIST = 0: direct search.  LIST = 1: walk the list of this step's density sweep.
+template <int DIM, bool MIXED, bool FUSED, int LIST>
+__global__ __launch_bounds__(kMaxBlock) void k_force(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
+    const int *__restrict__ wstart, const typename Rec<DIM, MIXED>::v4 *__restrict__ rec,
+    const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos, double *__restrict__ a,
+    double *__restrict__ v, const double *__restrict__ x, const double *__restrict__ rho,
+    const double *__restrict__ dt, double *__restrict__ partials, const uint4 *__restrict__ nlist,
+    const int *__restrict__ lcount, int cap)
+{
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    using v4 = typename V::v4;
+    constexpr int U = MIXED ? 4 : 2;
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    const bool act = k < ch.end;
+    const int n = sc.N;
+    const InstDev &I = inst[ch.inst];
+    const int kk = act ? k : ch.begin;
+    const v4 Ai = V::loadA(rec, kk);
+    const v4 Bi = V::loadB(rec, kk);
+    real pi[3], vi[3];
+    V::pos(Ai, pi);
+    V::vel(Ai, Bi, vi);
+    const real rho_i = V::rho(Bi), P_i = V::P(Bi);
+    const real p_i = P_i * rho_i * rho_i;
+    const real inv_rho_i2 = (real)1 / (rho_i * rho_i);
+    const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
+    const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
+    const real visc_a = (real)(sc.alpha * I.c0 * sc.h);
+    const real eps_h2 = MIXED ? (real)sc.feps_h2 : (real)sc.eps_h2;
+    const real gx = MIXED ? (real)sc.fg[0] : (real)sc.g[0];
+    const real gy = MIXED ? (real)sc.fg[1] : (real)sc.g[1];
+    const real gz = MIXED ? (real)sc.fg[2] : (real)sc.g[2];
+    real acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
+    int cnt = 0;
+    auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj)
+        __attribute__((always_inline)) {
+        // branch-free: lanes of a wave mix fluid and wall sources
+        real F;
+        kernel_F(r2, inv_h, kF, F);
+        real vj[3];
+        V::vel(Aj, Bj, vj);                // zero for walls
+        real vr = (vi[0] - vj[0]) * r[0] + (vi[1] - vj[1]) * r[1];
+        if constexpr (DIM == 3) vr += (vi[2] - vj[2]) * r[2];
+        real gr = gx * r[0] + gy * r[1];
+        if constexpr (DIM == 3) gr += gz * r[2];
+        real p_m = p_i - rho_i * gr;       // wall mirror: p_i + rho_i g.(x_j - x_i)
+        p_m = p_m < (real)0 ? (real)0 : p_m;
+        const real rho_j = wall ? rho_i : V::rho(Bj);
+        const real P_j = wall ? p_m * inv_rho_i2 : V::P(Bj);
+        real visc = 0;
+        if (vr < (real)0) {
+            const real den = (real)0.5 * (rho_i + rho_j) * (r2 + eps_h2);
+            if constexpr (MIXED) visc = -visc_a * vr * __builtin_amdgcn_rcpf(den);
+            else visc = -visc_a * vr / den;
+        }
+        const real coef = (P_i + P_j + visc) * F;
+        const real coef_ff = wall ? (real)0 : coef;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            acc[c] -= coef * r[c];
+            aff[c] -= coef_ff * r[c];
+        }
+        ++cnt;
+    };
+    if (act) {
+        const int lk = skey[k] - I.cell_base;
+        if constexpr (LIST) {
+            const int m = lcount[k];
+            if (m <= cap) walk_list<DIM, MIXED, U, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+            else for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        } else {
+            for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        }
+    }
+    double vals[kNPart];
+#pragma unroll
+    for (int q = 0; q < kNPart; ++q) vals[q] = 0.0;
+    if (act) {
+        const int i = perm[k];
+        double an[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            an[c] = sc.g[c] + sc.mass * (double)acc[c];
+            a[(int64_t)c * n + i] = an[c];
+            vals[P_FF + c] = sc.mass * (sc.mass * (double)aff[c]);
+        }
+        vals[P_PAIRS] = (double)cnt;
+        if constexpr (FUSED) {
+            const double dtb = dt[ch.inst];
+            double vn[DIM], xi[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                vn[c] = kick(v[(int64_t)c * n + i], an[c], dtb);
+                v[(int64_t)c * n + i] = vn[c];
+                xi[c] = x[(int64_t)c * n + i];
+            }
+            state_partials<DIM>(sc, I, vn, an, xi, rho[i], vals);
+        }
+    }
+    double *out = partials + (int64_t)ch.id * kNPart;
+    if constexpr (FUSED) block_partials<0, P_BAD + 1>(vals, out);
+    else block_partials<P_FF, P_PAIRS + 1>(vals, out);
+}
+
+template <int DIM, bool MIXED, bool FUSED, int LIST>
+static void force_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    using R = Rec<DIM, MIXED>;
+    k_force<DIM, MIXED, FUSED, LIST><<<d.nfchunks, d.block, 0, s>>>(
+        sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start,
+        static_cast<const typename R::v4 *>(d.rec), static_cast<const typename R::wpos_t *>(d.wpos), d.a, d.v,
+        d.x, d.rho, d.dt, d.partials, d.nlist, d.lcount, d.list_cap);
+}
+
+template <int DIM, bool MIXED>
+static void force_variant(const SimConst &sc, const Dev &d, int fused, int list, hipStream_t s)
+{
+    if (fused) { if (list) force_dispatch<DIM, MIXED, true, 1>(sc, d, s); else force_dispatch<DIM, MIXED, true, 0>(sc, d, s); }
+    else { if (list) force_dispatch<DIM, MIXED, false, 1>(sc, d, s); else force_dispatch<DIM, MIXED, false, 0>(sc, d, s); }
+}
+
+hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, int list, hipStream_t s)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) force_variant<2, true>(sc, d, fused, list, s); else force_variant<2, false>(sc, d, fused, list, s); }
+    else { if (mixed) force_variant<3, true>(sc, d, fused, list, s); else force_variant<3, false>(sc, d, fused, list, s); }
+    return hipGetLastError();
+}
+
+}  // namespace sphx

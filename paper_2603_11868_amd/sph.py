@@ -56,8 +56,8 @@ class sph_params(C.Structure):
                 ("rho0", C.c_double), ("alpha", C.c_double), ("eps", C.c_double),
                 ("cfl_ac", C.c_double), ("cfl_f", C.c_double), ("g", C.c_double * 3),
                 ("inst", C.POINTER(sph_instance_desc)), ("block_threads", C.c_int32),
-                ("queue_cap", C.c_int32), ("use_graph", C.c_int32), ("list_cap", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("use_graph", C.c_int32), ("list_cap", C.c_int32),
+                ("prefetch", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class sph_buffers(C.Structure):
@@ -233,8 +233,8 @@ class Simulation:
     """
 
     def __init__(self, case, precision="fp64", reorder_every=None, block_threads=0,
-                 queue_cap=0, use_graph=False, device="cuda", alpha=None, g=None,
-                 cfl=None, velocities=None, densities=None, list_cap=0):
+                 use_graph=False, device="cuda", alpha=None, g=None,
+                 cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0):
         import torch
         self.torch = torch
         self.case = case
@@ -265,9 +265,9 @@ class Simulation:
             p.g[a] = float(gv[a])
         p.inst = descs
         p.block_threads = int(block_threads)
-        p.queue_cap = int(queue_cap)
         p.use_graph = int(bool(use_graph))
         p.list_cap = int(list_cap)
+        p.prefetch = int(prefetch)
         self._descs = descs
         self.params = p
         self.precision = precision

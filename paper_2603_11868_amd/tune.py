@@ -1,7 +1,8 @@
 """Autotuner for the launch parameters of the hot path.
 
-Searches threads per sweep block, the per-thread hit-queue capacity of the
-sweeps (or plain direct search), and the reorder period K (how often the
+Searches threads per sweep block, the neighbour-list capacity (default, or
+plain direct search in both sweeps), the number of candidate records in
+flight per thread of the density sweep, and the reorder period K (how often the
 state arrays are physically re-sorted by cell; the cell table itself is
 rebuilt every step, so K changes results only through summation order).
 Each variant runs whole steps through the C ABI and is timed with HIP events
@@ -21,8 +22,8 @@ import time
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 BLOCKS = (64, 128, 256)
-QUEUES = (-1, 16, 32)
 LISTS = (0, -1)
+PREFETCHES = (4, 8)
 REORDERS = (1, 5, 20, 50)
 
 
@@ -31,12 +32,12 @@ def cache_key(arch, dim, precision, n_fluid):
     return f"{arch}/d{dim}/{precision}/n2^{bucket}"
 
 
-def time_variant(case, precision, block, queue, reorder, steps, warmup, list_cap=0):
+def time_variant(case, precision, block, list_cap, prefetch, reorder, steps, warmup):
     import torch
     from .sph import Simulation
 
-    sim = Simulation(case, precision=precision, block_threads=block, queue_cap=queue,
-                     reorder_every=reorder, list_cap=list_cap)
+    sim = Simulation(case, precision=precision, block_threads=block, list_cap=list_cap,
+                     prefetch=prefetch, reorder_every=reorder)
     try:
         sim.prime()
         sim.step(warmup)
@@ -53,21 +54,21 @@ def time_variant(case, precision, block, queue, reorder, steps, warmup, list_cap
         sim.close()
 
 
-def tune(case, precision="fp64", steps=20, warmup=3, blocks=BLOCKS, queues=QUEUES,
-         reorders=REORDERS, cache_path=DEFAULT_CACHE, log=print, lists=LISTS):
+def tune(case, precision="fp64", steps=20, warmup=3, blocks=BLOCKS, lists=LISTS,
+         prefetches=PREFETCHES, reorders=REORDERS, cache_path=DEFAULT_CACHE, log=print):
     """Time every variant; return the fastest as a dict and store it."""
     import torch
 
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     results = []
-    for block, lst, queue, reorder in itertools.product(blocks, lists, queues, reorders):
-        if lst >= 0 and queue != queues[0]:
-            continue          # with a list the force sweep has no traversal to queue
-        ms, flags = time_variant(case, precision, block, queue, reorder, steps, warmup, lst)
-        results.append({"block_threads": block, "list_cap": lst, "queue_cap": queue,
+    for block, lst, pf, reorder in itertools.product(blocks, lists, prefetches, reorders):
+        if lst < 0 and pf != prefetches[0]:
+            continue          # direct search has no list to prefetch for
+        ms, flags = time_variant(case, precision, block, lst, pf, reorder, steps, warmup)
+        results.append({"block_threads": block, "list_cap": lst, "prefetch": pf,
                         "reorder_every": reorder, "ms_per_step": round(ms, 5), "flags": flags})
         if log:
-            log(f"  block {block:3d} list {lst:3d} queue {queue:3d} K {reorder:3d}: {ms:8.4f} ms/step")
+            log(f"  block {block:3d} list {lst:3d} prefetch {pf} K {reorder:3d}: {ms:8.4f} ms/step")
     ok = [r for r in results if r["flags"] == 0]
     best = min(ok or results, key=lambda r: r["ms_per_step"])
     key = cache_key(arch, case.dim, precision, case.n_fluid)
@@ -105,15 +106,15 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--blocks", default=",".join(map(str, BLOCKS)))
-    ap.add_argument("--queues", default=",".join(map(str, QUEUES)))
+    ap.add_argument("--prefetches", default=",".join(map(str, PREFETCHES)))
     ap.add_argument("--reorders", default=",".join(map(str, REORDERS)))
     ap.add_argument("--lists", default=",".join(map(str, LISTS)))
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     args = ap.parse_args(argv)
     case = dambreak.make_case(args.case)
     ints = lambda s: tuple(int(v) for v in s.split(","))
-    e = tune(case, args.precision, args.steps, args.warmup, ints(args.blocks), ints(args.queues),
-             ints(args.reorders), args.cache, lists=ints(args.lists))
+    e = tune(case, args.precision, args.steps, args.warmup, ints(args.blocks), ints(args.lists),
+             ints(args.prefetches), ints(args.reorders), args.cache)
     print(json.dumps({"case": args.case, "precision": args.precision, "best": e["best"]}))
 
 

@@ -89,7 +89,7 @@ def test_argument_validation(sphmod):
     case = dambreak.make_case("tiny_2d")
     bad = [dict(dim=4), dict(precision=7), dict(n_instances=0), dict(dx=0.0), dict(h=-1.0),
            dict(block_threads=100), dict(reorder_every=-1), dict(eps=0.0),
-           dict(queue_cap=7), dict(list_cap=5000)]
+           dict(list_cap=5000), dict(prefetch=3)]
     for over in bad:
         p, descs = _params(sphmod, case, **over)
         with pytest.raises(sphmod.SphError, match="SPH_E_ARG"):

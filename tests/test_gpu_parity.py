@@ -300,14 +300,14 @@ def test_full_size_c2_against_reference():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_traversal_variants_agree(precision):
-    """Direct search, the queued traversal and the neighbour-list sweeps visit
-    the same neighbours in the same order: integers are identical; floats agree
+    """Direct search and the neighbour-list sweeps visit the same neighbours in
+    the same order: integers are identical; floats agree
     to round-off (the compiler may fuse multiply-adds differently per kernel).
     A list capacity below the neighbour count takes the overflow path."""
     from paper_2603_11868_amd import sph
     case = dambreak.make_case("tiny_3d")
-    variants = [dict(queue_cap=-1, list_cap=-1), dict(queue_cap=16, list_cap=-1),
-                dict(queue_cap=32, list_cap=-1), dict(), dict(list_cap=8)]
+    variants = [dict(list_cap=-1), dict(), dict(list_cap=8), dict(prefetch=4),
+                dict(list_cap=-1, block_threads=64)]
     hs, flags = [], []
     for kw in variants:
         s = _sim(case, precision=precision, **kw)
@@ -316,7 +316,7 @@ def test_traversal_variants_agree(precision):
         flags.append(s.poll_errors())
         hs.append(s.host())
         s.close()
-    assert flags[3] == 0 and flags[4] & sph.SPH_FLAG_CAPACITY
+    assert flags[1] == 0 and flags[2] & sph.SPH_FLAG_CAPACITY
     # FP32: a different fusion of one multiply-add moves rho by ~1e-7, which the
     # pressure amplifies ~1e4-fold on the near-lattice of the first steps
     rtol = 1e-12 if precision == "fp64" else 1e-3
