@@ -505,6 +505,10 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
             if (yy < 0 || yy >= ncy) continue;
             int xlo, xhi;
             if (!row_cells(o, cs, cut2m, dy, dz, c.cx, ncx, xlo, xhi)) continue;
+            // a needed row is scanned whole: targets of one cell then read the
+            // same candidates at the same time, one cache line for all of them
+            xlo = c.cx > 0 ? c.cx - 1 : c.cx;
+            xhi = c.cx < ncx - 1 ? c.cx + 1 : c.cx;
             const int row = I.cell_base + (yy + ncy * (c.cz + dz)) * ncx;
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
@@ -779,7 +783,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
-    constexpr int U = MIXED ? 4 : 2;
+    constexpr int U = 4;                   // list entries in flight per lane
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     const bool act = k < ch.end;
