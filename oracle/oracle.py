@@ -63,6 +63,20 @@ class _State(C.Structure):
     ]
 
 
+class _Dual(C.Structure):
+    _fields_ = [("cfl_adv", C.c_double), ("cfl_ac", C.c_double), ("eta", C.c_double)]
+
+
+class _DualState(C.Structure):
+    _fields_ = [("x_adv", _dp), ("drho", _dp), ("pres", _dp), ("a_ff", _dp),
+                ("Dt", C.c_double), ("dt", C.c_double), ("nsub", C.c_int)]
+
+
+# parameters of the dual-criteria scheme
+DUAL_CFL_ADV = 0.25
+DUAL_CFL_AC = 0.6
+DUAL_ETA = 3.0
+
 _lib = None
 
 
@@ -102,12 +116,40 @@ def lib():
         L.or_step.argtypes = ps + [C.c_int]
         L.or_num_threads.restype = C.c_int
         L.or_num_threads.argtypes = []
+        L.or_riemann.restype = None
+        L.or_riemann.argtypes = [C.c_double] * 8 + [_dp, _dp]
+        pd = [C.POINTER(_Params), C.POINTER(_Dual), C.POINTER(_State), C.POINTER(_DualState)]
+        L.or_dual_plan.restype = None
+        L.or_dual_plan.argtypes = pd
+        L.or_dual_summation.restype = None
+        L.or_dual_summation.argtypes = [pd[0], pd[2], pd[3]]
+        L.or_dual_first_half.restype = None
+        L.or_dual_first_half.argtypes = [pd[0], pd[2], pd[3], C.c_double]
+        L.or_dual_pressure.restype = None
+        L.or_dual_pressure.argtypes = pd + [C.c_double]
+        L.or_dual_second_half.restype = None
+        L.or_dual_second_half.argtypes = [pd[0], pd[2], C.c_double]
+        L.or_dual_density.restype = None
+        L.or_dual_density.argtypes = pd + [C.c_double]
+        L.or_dual_prime.restype = C.c_int
+        L.or_dual_prime.argtypes = pd
+        L.or_dual_step.restype = C.c_int
+        L.or_dual_step.argtypes = pd + [C.c_int]
         _lib = L
     return _lib
 
 
 def num_threads():
     return int(lib().or_num_threads())
+
+
+def riemann(rho_l, p_l, u_l, rho_r, p_r, u_r, c0, eta=DUAL_ETA):
+    """Interface pressure and normal velocity of the acoustic Riemann problem
+    between a left and a right state (dissipation limited by eta)."""
+    ps, us = C.c_double(), C.c_double()
+    lib().or_riemann(float(rho_l), float(p_l), float(u_l), float(rho_r), float(p_r), float(u_r),
+                     float(c0), float(eta), C.byref(ps), C.byref(us))
+    return ps.value, us.value
 
 
 def W(dim, h, r):
@@ -260,6 +302,55 @@ class OracleSim:
         return lib().or_step(C.byref(self.p), C.byref(self.s), int(nsteps))
 
     # -- views indexed by particle id -------------------------------------
+    # -- second scheme: dual-criteria time stepping ---------------------
+    def _dual(self):
+        if getattr(self, "_dstate", None) is None:
+            n, dim = max(self.n, 1), self.dim
+            self.x_adv = np.zeros((n, dim))
+            self.drho = np.zeros(n)
+            self.pres = np.zeros(n)
+            self.a_ff_dual = np.zeros((n, dim))
+            ds = _DualState()
+            ds.x_adv, ds.drho, ds.pres, ds.a_ff = (_d(self.x_adv), _d(self.drho), _d(self.pres),
+                                                   _d(self.a_ff_dual))
+            self._dstate = ds
+            dp = _Dual()
+            dp.cfl_adv, dp.cfl_ac, dp.eta = DUAL_CFL_ADV, DUAL_CFL_AC, DUAL_ETA
+            self._dparams = dp
+        return self._dparams, self._dstate
+
+    def dual_prime(self):
+        dp, ds = self._dual()
+        return lib().or_dual_prime(C.byref(self.p), C.byref(dp), C.byref(self.s), C.byref(ds))
+
+    def dual_step(self, nsteps=1):
+        """nsteps advection steps, each with its acoustic sub-steps."""
+        dp, ds = self._dual()
+        return lib().or_dual_step(C.byref(self.p), C.byref(dp), C.byref(self.s), C.byref(ds), int(nsteps))
+
+    def dual_plan(self):
+        """(advection step, sub-steps, sub-step) of the next advection step."""
+        dp, ds = self._dual()
+        return ds.Dt, ds.nsub, ds.dt
+
+    def dual_stage(self, name, dt=0.0):
+        """One stage of the second scheme (summation, first_half, pressure,
+        second_half, density), for tests."""
+        dp, ds = self._dual()
+        L, P, S = lib(), C.byref(self.p), C.byref(self.s)
+        if name == "summation":
+            L.or_dual_summation(P, S, C.byref(ds))
+        elif name == "first_half":
+            L.or_dual_first_half(P, S, C.byref(ds), float(dt))
+        elif name == "pressure":
+            L.or_dual_pressure(P, C.byref(dp), S, C.byref(ds), float(dt))
+        elif name == "second_half":
+            L.or_dual_second_half(P, S, float(dt))
+        elif name == "density":
+            L.or_dual_density(P, C.byref(dp), S, C.byref(ds), float(dt))
+        else:
+            raise ValueError(name)
+
     def by_id(self, arr):
         out = np.empty_like(arr)
         out[self.id] = arr

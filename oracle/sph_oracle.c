@@ -233,10 +233,21 @@ static void cell_coords(const or_params *p, int32_t key, int c[3])
  * top of the file.  kind = 0 for fluid sources, 1 for walls. */
 typedef void (*pair_fn)(void *ctx, int kind, int j, double r2, const double *r);
 
+/* The same with the fluid positions taken from xf (the table must have been
+ * built at those positions). */
+static void for_neighbours_at(const or_params *p, const or_state *s, const double *xf, int i, pair_fn fn,
+                              void *ctx);
+
 static void for_neighbours(const or_params *p, const or_state *s, int i, pair_fn fn, void *ctx)
 {
+    for_neighbours_at(p, s, s->x, i, fn, ctx);
+}
+
+static void for_neighbours_at(const or_params *p, const or_state *s, const double *xf, int i, pair_fn fn,
+                              void *ctx)
+{
     int dim = p->dim;
-    const double *xi = s->x + (long)i * dim;
+    const double *xi = xf + (long)i * dim;
     int c[3];
     cell_coords(p, s->key[i], c);
     int dz_lo = (dim == 3) ? -1 : 0, dz_hi = (dim == 3) ? 1 : 0;
@@ -254,7 +265,7 @@ static void for_neighbours(const or_params *p, const or_state *s, int i, pair_fn
                 for (int k = s->start[cell]; k < s->start[cell + 1]; ++k) {
                     int j = s->perm[k];
                     if (j == i) continue;
-                    double r2 = dist2(dim, xi, s->x + (long)j * dim, r);
+                    double r2 = dist2(dim, xi, xf + (long)j * dim, r);
                     if (r2 < p->cut2) fn(ctx, 0, j, r2, r);
                 }
                 for (int k = s->wstart[cell]; k < s->wstart[cell + 1]; ++k) {
@@ -503,5 +514,260 @@ int or_step(const or_params *p, or_state *s, int nsteps)
         total_clamped += cl;
     }
     free(a_ff);
+    return total_clamped;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dual-criteria time stepping with a Riemann-solver pressure (second       */
+/* scheme).                                                                 */
+/*                                                                          */
+/* The library behind the paper (SPHinXsys) advances weakly compressible     */
+/* flow with two time-step criteria: an advection step Dt that rebuilds the  */
+/* cell table and the neighbour configuration and resets the density by      */
+/* summation, and several acoustic sub-steps dt inside it that relax          */
+/* pressure and density against the configuration frozen at the advection   */
+/* step, with interface states from a linearised (acoustic) Riemann problem   */
+/* along each pair in place of artificial viscosity (Zhang, Hu & Adams 2017;  */
+/* Zhang, Rezavand & Hu 2021).  Written here from that description:           */
+/*                                                                          */
+/*   advection   keys, sort, ranges (reorder every K advection steps) at x;  */
+/*               x_adv <- x; density by summation with the free-surface      */
+/*               rule (or_density with dt = 0); Drho <- 0.                    */
+/*               Dt = C_adv h / max(max|v|, U_ref), U_ref = c0 / 10;          */
+/*               n = ceil(Dt / (C_ac' h / (c0 + max|v|))), dt = Dt / n, with  */
+/*               max|v| taken at the end of the previous advection step.      */
+/*   sub-step    rho += dt/2 Drho;  p = max(0, c0^2 (rho - rho0));  x += dt/2 v;*/
+/*               a_i = g - 2 sum_j m P*_ij / (rho_i rho_j) grad_i W_ij;       */
+/*               v += dt a;  x += dt/2 v;                                     */
+/*               Drho_i = 2 rho_i sum_j (m / rho_j) (v_i - v*_ij).grad_i W_ij; */
+/*               rho += dt/2 Drho.                                            */
+/*   geometry    grad_i W_ij = F_ij r_ij and e_ij = r_ij / |r_ij| from x_adv  */
+/*               (the frozen configuration), for all sub-steps.               */
+/*   Riemann     along e = e_ij: U_L = -v_i.e, U_R = -v_j.e, Z = rho c0;      */
+/*               beta = min(eta max(U_L - U_R, 0) / c0, 1), eta = 3;          */
+/*               P* = (Z_L p_R + Z_R p_L + Z_L Z_R beta (U_L - U_R)) / (Z_L + Z_R);*/
+/*               v* = (Z_L v_i + Z_R v_j) / (Z_L + Z_R) - (p_L - p_R) / (Z_L + Z_R) e.*/
+/*   walls       rho_j = rho_i, p_j = max(0, p_i + rho_i g.(x_j - x_i^adv)), v_j = 0.*/
+/* Each sweep computes all targets from the previous values before any is    */
+/* updated (gathers into scratch, then the update).                          */
+/* ------------------------------------------------------------------------ */
+
+void or_riemann(double rho_l, double p_l, double u_l, double rho_r, double p_r, double u_r, double c0,
+                double eta, double *p_star, double *u_star)
+{
+    double zl = rho_l * c0, zr = rho_r * c0;
+    double du = u_l - u_r;
+    double beta = eta * (du > 0.0 ? du : 0.0) / c0;
+    if (beta > 1.0) beta = 1.0;
+    double zs = zl + zr;
+    *p_star = (zl * p_r + zr * p_l + zl * zr * beta * du) / zs;
+    *u_star = (zl * u_l + zr * u_r + (p_l - p_r)) / zs;
+}
+
+void or_dual_plan(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d)
+{
+    double vmax = s->diag[0];
+    double uref = p->c0 / 10.0;
+    double Dt = dp->cfl_adv * p->h / (vmax > uref ? vmax : uref);
+    double dac = dp->cfl_ac * p->h / (p->c0 + vmax);
+    int nsub = (int)ceil(Dt / dac);
+    if (nsub < 1) nsub = 1;
+    d->Dt = Dt;
+    d->nsub = nsub;
+    d->dt = Dt / (double)nsub;
+    s->dt[0] = Dt;
+}
+
+static double eos_clipped(const or_params *p, double rho)
+{
+    double pr = p->c0 * p->c0 * (rho - p->rho0);
+    return pr < 0.0 ? 0.0 : pr;
+}
+
+void or_dual_summation(const or_params *p, or_state *s, or_dual_state *d)
+{
+    or_density(p, s, 0.0);
+    memcpy(d->x_adv, s->x, sizeof(double) * (size_t)s->n * p->dim);
+    for (int i = 0; i < s->n; ++i) d->drho[i] = 0.0;
+}
+
+void or_dual_first_half(const or_params *p, or_state *s, or_dual_state *d, double dt)
+{
+    int dim = p->dim;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i) {
+        s->rho[i] = s->rho[i] + 0.5 * dt * d->drho[i];
+        d->pres[i] = eos_clipped(p, s->rho[i]);
+        for (int a = 0; a < dim; ++a) {
+            long k = (long)i * dim + a;
+            s->x[k] = s->x[k] + 0.5 * dt * s->v[k];
+        }
+    }
+}
+
+typedef struct {
+    const or_params *p;
+    const or_dual *dp;
+    const or_state *s;
+    const or_dual_state *d;
+    int i;
+    double acc[3], acc_ff[3], drho;
+} dual_ctx;
+
+/* Interface state of pair (i, j): pressure P* and the velocity jump v_i - v*. */
+static void dual_pair_state(dual_ctx *c, int kind, int j, double r2, const double *r, double *pstar,
+                            double *dv, double *rho_j_out)
+{
+    const or_params *p = c->p;
+    const or_state *s = c->s;
+    const or_dual_state *d = c->d;
+    int dim = p->dim, i = c->i;
+    double rho_i = s->rho[i], p_i = d->pres[i];
+    double rho_j, p_j, vj[3] = {0.0, 0.0, 0.0};
+    if (kind == 0) {
+        rho_j = s->rho[j];
+        p_j = d->pres[j];
+        for (int a = 0; a < dim; ++a) vj[a] = s->v[(long)j * dim + a];
+    } else {
+        double gx = 0.0;
+        for (int a = 0; a < dim; ++a) gx += p->g[a] * (s->xw[(long)j * dim + a] - d->x_adv[(long)i * dim + a]);
+        p_j = p_i + rho_i * gx;
+        if (p_j < 0.0) p_j = 0.0;
+        rho_j = rho_i;
+    }
+    double rr = sqrt(r2);
+    double e[3] = {0.0, 0.0, 0.0};
+    if (rr > 0.0)
+        for (int a = 0; a < dim; ++a) e[a] = r[a] / rr;
+    const double *vi = s->v + (long)i * dim;
+    double ul = 0.0, ur = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        ul -= vi[a] * e[a];
+        ur -= vj[a] * e[a];
+    }
+    double ps, us;
+    or_riemann(rho_i, p_i, ul, rho_j, p_j, ur, p->c0, c->dp->eta, &ps, &us);
+    double zl = rho_i * p->c0, zr = rho_j * p->c0, zs = zl + zr;
+    /* v_i - v* = Z_R (v_i - v_j) / (Z_L + Z_R) + (p_L - p_R) / (Z_L + Z_R) e */
+    for (int a = 0; a < dim; ++a) dv[a] = zr * (vi[a] - vj[a]) / zs + (p_i - p_j) / zs * e[a];
+    *pstar = ps;
+    *rho_j_out = rho_j;
+}
+
+static void dual_force_pair(void *vc, int kind, int j, double r2, const double *r)
+{
+    dual_ctx *c = (dual_ctx *)vc;
+    const or_params *p = c->p;
+    int dim = p->dim;
+    double ps, dv[3], rho_j;
+    dual_pair_state(c, kind, j, r2, r, &ps, dv, &rho_j);
+    double F = or_F(dim, p->h, sqrt(r2));
+    double coef = 2.0 * p->mass * ps / (c->s->rho[c->i] * rho_j) * F;
+    for (int a = 0; a < dim; ++a) {
+        c->acc[a] -= coef * r[a];
+        if (kind == 0) c->acc_ff[a] -= coef * r[a];
+    }
+}
+
+void or_dual_pressure(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d, double dt)
+{
+    int dim = p->dim;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < s->n; ++i) {
+        dual_ctx c;
+        c.p = p; c.dp = dp; c.s = s; c.d = d; c.i = i; c.drho = 0.0;
+        for (int a = 0; a < 3; ++a) { c.acc[a] = 0.0; c.acc_ff[a] = 0.0; }
+        for_neighbours_at(p, s, d->x_adv, i, dual_force_pair, &c);
+        for (int a = 0; a < dim; ++a) {
+            s->a[(long)i * dim + a] = p->g[a] + c.acc[a];
+            d->a_ff[(long)i * dim + a] = c.acc_ff[a];
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i)
+        for (int a = 0; a < dim; ++a) {
+            long k = (long)i * dim + a;
+            s->v[k] = s->v[k] + dt * s->a[k];
+        }
+}
+
+void or_dual_second_half(const or_params *p, or_state *s, double dt)
+{
+    int dim = p->dim;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i)
+        for (int a = 0; a < dim; ++a) {
+            long k = (long)i * dim + a;
+            s->x[k] = s->x[k] + 0.5 * dt * s->v[k];
+        }
+}
+
+static void dual_density_pair(void *vc, int kind, int j, double r2, const double *r)
+{
+    dual_ctx *c = (dual_ctx *)vc;
+    const or_params *p = c->p;
+    int dim = p->dim;
+    double ps, dv[3], rho_j;
+    dual_pair_state(c, kind, j, r2, r, &ps, dv, &rho_j);
+    double F = or_F(dim, p->h, sqrt(r2));
+    double dot = 0.0;
+    for (int a = 0; a < dim; ++a) dot += dv[a] * r[a];
+    c->drho += p->mass / rho_j * dot * F;
+}
+
+void or_dual_density(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d, double dt)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < s->n; ++i) {
+        dual_ctx c;
+        c.p = p; c.dp = dp; c.s = s; c.d = d; c.i = i; c.drho = 0.0;
+        for (int a = 0; a < 3; ++a) { c.acc[a] = 0.0; c.acc_ff[a] = 0.0; }
+        for_neighbours_at(p, s, d->x_adv, i, dual_density_pair, &c);
+        d->drho[i] = 2.0 * s->rho[i] * c.drho;
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i) s->rho[i] = s->rho[i] + 0.5 * dt * d->drho[i];
+}
+
+static void dual_substep(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d, double dt)
+{
+    or_dual_first_half(p, s, d, dt);
+    or_dual_pressure(p, dp, s, d, dt);
+    or_dual_second_half(p, s, dt);
+    or_dual_density(p, dp, s, d, dt);
+}
+
+/* Table and summation at x0, one pressure sweep with v = 0 (for the
+ * diagnostics), reductions, and the plan of the first advection step. */
+int or_dual_prime(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d)
+{
+    int cl = or_keys(p, s->n, s->x, s->key);
+    or_sort(s->n, s->key, p->ncells, s->perm, s->start);
+    or_dual_summation(p, s, d);
+    for (int i = 0; i < s->n; ++i) d->pres[i] = eos_clipped(p, s->rho[i]);
+    or_dual_pressure(p, dp, s, d, 0.0);
+    or_reduce(p, s, d->a_ff, cl, 0.0);
+    s->diag[15] = 0.0;
+    *s->step = 0;
+    or_dual_plan(p, dp, s, d);
+    return cl;
+}
+
+int or_dual_step(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d, int nsteps)
+{
+    int total_clamped = 0;
+    for (int it = 0; it < nsteps; ++it) {
+        int cl = or_keys(p, s->n, s->x, s->key);
+        or_sort(s->n, s->key, p->ncells, s->perm, s->start);
+        if (p->reorder_every > 0 && (*s->step % p->reorder_every) == 0) or_reorder(p, s);
+        or_dual_summation(p, s, d);
+        double Dt = d->Dt;
+        for (int k = 0; k < d->nsub; ++k) dual_substep(p, dp, s, d, d->dt);
+        or_reduce(p, s, d->a_ff, cl, Dt);
+        *s->step += 1;
+        s->diag[15] = (double)*s->step;
+        or_dual_plan(p, dp, s, d);
+        total_clamped += cl;
+    }
     return total_clamped;
 }

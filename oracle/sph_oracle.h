@@ -82,6 +82,34 @@ void or_half1(const or_params *p, or_state *s, double dt);
 void or_half2(const or_params *p, or_state *s, double dt);
 void or_reduce(const or_params *p, or_state *s, const double *a_ff, int clamped, double dt_used);
 
+/* Second scheme: dual-criteria time stepping with a Riemann-solver pressure
+ * (definitions in sph_oracle.c). */
+typedef struct {
+    double cfl_adv;          /* advection Courant number (0.25) */
+    double cfl_ac;           /* acoustic Courant number (0.6) */
+    double eta;              /* dissipation limiter slope (3) */
+} or_dual;
+
+typedef struct {
+    double *x_adv;           /* n*dim positions of the frozen configuration */
+    double *drho;            /* n continuity rate of the last second half */
+    double *pres;            /* n pressure of the current sub-step */
+    double *a_ff;            /* n*dim fluid-fluid part of the last pressure sweep */
+    double Dt, dt;           /* advection step and its sub-step */
+    int nsub;                /* sub-steps per advection step */
+} or_dual_state;
+
+void or_riemann(double rho_l, double p_l, double u_l, double rho_r, double p_r, double u_r, double c0,
+                double eta, double *p_star, double *u_star);
+void or_dual_plan(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d);
+void or_dual_summation(const or_params *p, or_state *s, or_dual_state *d);
+void or_dual_first_half(const or_params *p, or_state *s, or_dual_state *d, double dt);
+void or_dual_pressure(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d, double dt);
+void or_dual_second_half(const or_params *p, or_state *s, double dt);
+void or_dual_density(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d, double dt);
+int or_dual_prime(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d);
+int or_dual_step(const or_params *p, const or_dual *dp, or_state *s, or_dual_state *d, int nsteps);
+
 /* Whole steps. */
 int or_bind_walls(const or_params *p, or_state *s);
 int or_prime(const or_params *p, or_state *s);
