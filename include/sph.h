@@ -63,6 +63,12 @@ typedef enum {
 } sph_status;
 
 typedef enum {
+    SPH_SCHEME_WCSPH = 0,    /* the step described at the top of this file */
+    SPH_SCHEME_DUAL = 1      /* dual-criteria time stepping with an acoustic
+                                Riemann-solver pressure (below) */
+} sph_scheme;
+
+typedef enum {
     SPH_FP64 = 0,            /* all arithmetic in FP64 */
     SPH_MIXED = 1            /* FP32 pair sweeps on FP32 offsets from FP64 cell
                                 origins; FP64 state, integration and reductions */
@@ -122,6 +128,14 @@ typedef struct {
                                 from sph_create). */
     int32_t prefetch;        /* candidate records in flight per thread in the
                                 density sweep: 0 = default (8), 4 or 8 */
+    int32_t scheme;          /* sph_scheme.  SPH_SCHEME_DUAL needs SPH_FP64 and
+                                use_graph = 0; cfl_ac is then the Courant number
+                                of the acoustic sub-steps (0.6 in the published
+                                scheme), alpha, eps and cfl_f are unused */
+    int32_t reserved0;
+    double cfl_adv;          /* SPH_SCHEME_DUAL: advection Courant number (0.25) */
+    double eta;              /* SPH_SCHEME_DUAL: slope of the Riemann dissipation
+                                limiter (3) */
     int32_t reserved[4];
 } sph_params;
 
@@ -217,8 +231,39 @@ sph_status sph_integrate(sph_ctx *ctx, int32_t half, void *stream);
 
 /* n_steps full steps of every instance: half 1 + keys, sort (with the reorder
  * on steps where steps_done % K == 0), density, force fused with half 2,
- * reductions.  dt stays on the device; asynchronous. */
+ * reductions.  dt stays on the device; asynchronous.
+ *
+ * With SPH_SCHEME_DUAL a step is one advection step of every instance, and
+ * each advection step reads the largest planned sub-step count back to the
+ * host (one synchronisation of `stream` per step).  The scheme (the library
+ * behind the paper, SPHinXsys; Zhang, Hu & Adams 2017 and Zhang, Rezavand &
+ * Hu 2021 for the published method):
+ *   advection  keys, sort, ranges (reorder every K advection steps) and the
+ *              sweep records at x, which stay frozen for the sub-steps;
+ *              density by summation as in sph_prime; Drho <- 0;
+ *              Dt = cfl_adv h / max(max|v|, c0 / 10),
+ *              n = ceil(Dt / (cfl_ac h / (c0 + max|v|))), dt = Dt / n, with
+ *              max|v| from the previous reductions (dt[] holds Dt);
+ *   sub-step   rho += dt/2 Drho; p = max(0, c0^2 (rho - rho0)); x += dt/2 v;
+ *              a_i = g - 2 m sum_j P*_ij / (rho_i rho_j) grad_i W_ij; v += dt a;
+ *              x += dt/2 v;
+ *              Drho_i = 2 rho_i m sum_j (v_i - v*_ij).grad_i W_ij / rho_j;
+ *              rho += dt/2 Drho;  with grad_i W_ij = F_ij r_ij and
+ *              e = r_ij / |r_ij| from the frozen configuration;
+ *   Riemann    U_L = -v_i.e, U_R = -v_j.e, Z = rho c0,
+ *              beta = min(eta max(U_L - U_R, 0) / c0, 1),
+ *              P* = (Z_L p_R + Z_R p_L + Z_L Z_R beta (U_L - U_R)) / (Z_L + Z_R),
+ *              v* = (Z_L v_i + Z_R v_j) / (Z_L + Z_R) - (p_L - p_R) / (Z_L + Z_R) e;
+ *   walls      rho_j = rho_i, v_j = 0, p_j = max(0, p_i + rho_i g.(x_j - x_i));
+ *   then the reductions (diag as above, a and the force residual from the
+ *   last sub-step) and the plan of the next advection step.
+ * The stage calls (sph_build_cells ... sph_integrate) are for
+ * SPH_SCHEME_WCSPH only and return SPH_E_UNSUPPORTED otherwise. */
 sph_status sph_step_batched(sph_ctx *ctx, int32_t n_steps, void *stream);
+
+/* SPH_SCHEME_DUAL: the acoustic sub-step count of the next advection step of
+ * each instance (n[0..B-1]).  Synchronises `stream`. */
+sph_status sph_substeps(sph_ctx *ctx, int32_t *n, void *stream);
 
 /* Synchronise `stream`, return the sticky device flags and clear them. */
 sph_status sph_poll_errors(sph_ctx *ctx, uint32_t *flags, void *stream);

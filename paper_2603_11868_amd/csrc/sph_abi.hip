@@ -29,9 +29,11 @@ sph_status fail(sph_status st, const std::string &msg)
             return fail(SPH_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-enum Stage { ST_KEYS = 0, ST_SCAN, ST_SORT, ST_REORDER, ST_PACK, ST_DENSITY, ST_FORCE, ST_REDUCE, ST_COUNT };
+enum Stage { ST_KEYS = 0, ST_SCAN, ST_SORT, ST_REORDER, ST_PACK, ST_DENSITY, ST_FORCE, ST_REDUCE,
+             ST_SUB_FIRST, ST_SUB_PRESSURE, ST_SUB_SECOND, ST_SUB_DENSITY, ST_COUNT };
 const char *kStageNames[ST_COUNT] = {"keys", "cell_scan", "radix_sort", "reorder",
-                                     "pack", "density", "force", "reduce"};
+                                     "pack", "density", "force", "reduce",
+                                     "sub_first_half", "sub_pressure", "sub_second_half", "sub_density"};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -93,11 +95,12 @@ struct sph_ctx {
     int pref = 8;
     bool list_valid = false;  // the neighbour list matches the current sorted order
     bool mixed = false;
+    bool dual = false;        // dual-criteria Riemann scheme
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
         o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
-        o_lcount, o_cpos, o_wcpos;
+        o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax;
     // state
     bool bound = false, primed = false, cells_built = false;
     sph_buffers buf{};
@@ -210,6 +213,11 @@ void build_layout(sph_ctx *c)
     c->o_cpos = take(c->mixed ? 1 : nf * cbytes);
     c->o_wcpos = take(c->mixed ? 1 : (size_t)std::max<int64_t>(c->Nw, 1) * cbytes);
     c->o_nlist = take(c->lcap > 0 ? sizeof(unsigned) * nf * (size_t)c->lcap : 1);
+    // dual scheme: continuity rates and the per-instance sub-step plan
+    c->o_drho = take(c->dual ? sizeof(double) * nf : 1);
+    c->o_nsub = take(sizeof(int) * c->idev.size());
+    c->o_dtsub = take(sizeof(double) * c->idev.size());
+    c->o_nsubmax = take(sizeof(int));
     c->ws_bytes = off;
 }
 
@@ -318,6 +326,67 @@ sph_status do_reduce(sph_ctx *c, int prime, hipStream_t s, bool timed)
     return check_launch(launch_final_reduce(c->sc, c->dev, prime, s), "reduce");
 }
 
+bool reorder_due(const sph_ctx *c)
+{
+    return c->p.reorder_every > 0 && (c->steps_done % c->p.reorder_every) == 0;
+}
+
+// ---- dual-criteria scheme ------------------------------------------------
+
+sph_status do_dual_part(sph_ctx *c, int sub, int part, hipStream_t s, bool timed)
+{
+    static const Stage stage[4] = {ST_SUB_FIRST, ST_SUB_PRESSURE, ST_SUB_SECOND, ST_SUB_DENSITY};
+    const int list = c->lcap > 0 && c->list_valid;
+    StageTimer t(c, stage[part], s, timed);
+    return check_launch(launch_dual_substep(c->sc, c->dev, sub, list, s, part), "dual sub-step");
+}
+
+// State partials, then the per-instance reductions with the plan of the
+// next advection step (and its maximum sub-step count).
+sph_status dual_reduce(sph_ctx *c, int prime, hipStream_t s, bool timed)
+{
+    const Dev &d = c->dev;
+    TRY(check_launch(launch_half2(c->sc, d, s, 0), "state partials"));
+    TRY(check_launch(launch_fill_i32(d.nsub_max, 1, 0, s), "plan reset"));
+    return do_reduce(c, prime, s, timed);
+}
+
+// Step 0: cell table and summation at x0, pressure and the pressure sweep
+// with dt = 0, reductions and the first plan.
+sph_status dual_prime(sph_ctx *c, hipStream_t s)
+{
+    const Dev &d = c->dev;
+    const int64_t B = (int64_t)c->idev.size();
+    TRY(do_keys(c, 0, s, false));
+    TRY(do_sort(c, false, s, false));
+    TRY(do_density(c, 0, s, false));
+    TRY(check_launch(launch_fill_f64(d.drho, c->N, 0.0, s), "fill"));
+    TRY(check_launch(launch_fill_i32(d.nsub, B, 1, s), "fill"));
+    TRY(check_launch(launch_fill_f64(d.dtsub, B, 0.0, s), "fill"));
+    TRY(do_dual_part(c, 0, 0, s, false));
+    TRY(do_dual_part(c, 0, 1, s, false));
+    return dual_reduce(c, 1, s, false);
+}
+
+// One advection step: cell table, records and summation (with the list) at
+// the current positions, then the planned acoustic sub-steps.  Reads the
+// largest sub-step count back to the host first (one synchronisation).
+sph_status dual_advection_step(sph_ctx *c, hipStream_t s, bool timed)
+{
+    const Dev &d = c->dev;
+    int nmax = 0;
+    HIP_TRY(hipMemcpyAsync(&nmax, d.nsub_max, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (nmax < 1 || nmax > (1 << 20)) return fail(SPH_E_STATE, "invalid sub-step plan (non-finite velocities?)");
+    TRY(do_keys(c, 0, s, timed));
+    TRY(do_sort(c, reorder_due(c), s, timed));
+    TRY(do_density(c, 0, s, timed));
+    TRY(check_launch(launch_fill_f64(d.drho, c->N, 0.0, s), "fill"));
+    for (int sub = 0; sub < nmax; ++sub)
+        for (int part = 0; part < 4; ++part) TRY(do_dual_part(c, sub, part, s, timed));
+    return dual_reduce(c, 0, s, timed);
+}
+
 sph_status enqueue_step(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
 {
     TRY(do_keys(c, 1, s, timed));
@@ -325,11 +394,6 @@ sph_status enqueue_step(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
     TRY(do_density(c, 1, s, timed));
     TRY(do_force(c, 1, s, timed));
     return do_reduce(c, 0, s, timed);
-}
-
-bool reorder_due(const sph_ctx *c)
-{
-    return c->p.reorder_every > 0 && (c->steps_done % c->p.reorder_every) == 0;
 }
 
 sph_status ensure_graph(sph_ctx *c, int variant)
@@ -399,6 +463,13 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     const int pref = p->prefetch == 0 ? 8 : p->prefetch;
     if (pref != 4 && pref != 8) return fail(SPH_E_ARG, "prefetch must be 0, 4 or 8");
     if (lcap > 4096) return fail(SPH_E_ARG, "list_cap must be at most 4096");
+    if (p->scheme != SPH_SCHEME_WCSPH && p->scheme != SPH_SCHEME_DUAL) return fail(SPH_E_ARG, "unknown scheme");
+    if (p->scheme == SPH_SCHEME_DUAL) {
+        if (p->precision != SPH_FP64) return fail(SPH_E_UNSUPPORTED, "the dual scheme runs in FP64 only");
+        if (p->use_graph) return fail(SPH_E_UNSUPPORTED, "the dual scheme does not replay graphs");
+        if (!(p->cfl_adv > 0.0) || !(p->eta >= 0.0))
+            return fail(SPH_E_ARG, "the dual scheme needs cfl_adv > 0 and eta >= 0");
+    }
     auto *c = new sph_ctx();
     c->p = *p;
     c->p.inst = nullptr;
@@ -406,6 +477,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     c->lcap = lcap;
     c->pref = pref;
     c->mixed = p->precision == SPH_MIXED;
+    c->dual = p->scheme == SPH_SCHEME_DUAL;
     c->inst.assign(p->inst, p->inst + p->n_instances);
     const double cs = 2.0 * p->h;
     int64_t N = 0, Nw = 0, C = 0;
@@ -458,6 +530,10 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     sc.kF = -5.0 * ka / (p->h * p->h);
     sc.W0 = ka;
     for (int a = 0; a < 3; ++a) sc.g[a] = p->g[a];
+    sc.scheme = c->dual ? 1 : 0;
+    sc.cfl_adv = c->dual ? p->cfl_adv : 0.0;
+    sc.cfl_sub = p->cfl_ac;
+    sc.eta = c->dual ? p->eta : 0.0;
     sc.fh = (float)sc.h;
     sc.finv_h = (float)sc.inv_h;
     sc.fcs = (float)cs;
@@ -565,6 +641,10 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.prefetch = c->pref;
     d.nlist = reinterpret_cast<uint4 *>(ws + c->o_nlist);
     d.lcount = reinterpret_cast<int *>(ws + c->o_lcount);
+    d.drho = reinterpret_cast<double *>(ws + c->o_drho);
+    d.nsub = reinterpret_cast<int *>(ws + c->o_nsub);
+    d.dtsub = reinterpret_cast<double *>(ws + c->o_dtsub);
+    d.nsub_max = reinterpret_cast<int *>(ws + c->o_nsubmax);
     if (!c->fmap.empty())
         HIP_TRY(hipMemcpyAsync(d.fmap, c->fmap.data(), sizeof(Chunk) * c->fmap.size(), hipMemcpyHostToDevice, s));
     if (!c->wmap.empty())
@@ -597,12 +677,16 @@ sph_status sph_prime(sph_ctx *c, void *stream)
     const Dev &d = c->dev;
     HIP_TRY(launch_fill_f64(d.diag, (int64_t)c->idev.size() * SPH_NDIAG, 0.0, s));
     HIP_TRY(launch_fill_i32(d.cnt, c->C + 1, 0, s));
-    TRY(do_keys(c, 0, s, false));
-    TRY(do_sort(c, false, s, false));
-    TRY(do_density(c, 0, s, false));
-    TRY(do_force(c, 0, s, false));
-    TRY(check_launch(launch_half2(c->sc, d, s, 0), "state partials"));
-    TRY(do_reduce(c, 1, s, false));
+    if (c->dual) {
+        TRY(dual_prime(c, s));
+    } else {
+        TRY(do_keys(c, 0, s, false));
+        TRY(do_sort(c, false, s, false));
+        TRY(do_density(c, 0, s, false));
+        TRY(do_force(c, 0, s, false));
+        TRY(check_launch(launch_half2(c->sc, d, s, 0), "state partials"));
+        TRY(do_reduce(c, 1, s, false));
+    }
     c->primed = true;
     c->cells_built = false;
     c->steps_done = 0;
@@ -613,6 +697,7 @@ sph_status sph_build_cells(sph_ctx *c, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (c->cells_built) return fail(SPH_E_STATE, "cells already built: call sph_sort first");
     TRY(do_keys(c, 0, as_stream(stream), c->timing));
     c->cells_built = true;
@@ -623,6 +708,7 @@ sph_status sph_sort(sph_ctx *c, int32_t reorder, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (!c->cells_built) return fail(SPH_E_STATE, "sph_build_cells (or sph_integrate half 1) first");
     TRY(do_sort(c, reorder != 0, as_stream(stream), c->timing));
     c->cells_built = false;
@@ -633,6 +719,7 @@ sph_status sph_density(sph_ctx *c, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     return do_density(c, 1, as_stream(stream), c->timing);
 }
 
@@ -640,6 +727,7 @@ sph_status sph_forces(sph_ctx *c, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     return do_force(c, 0, as_stream(stream), c->timing);
 }
 
@@ -647,6 +735,7 @@ sph_status sph_integrate(sph_ctx *c, int32_t half, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (half != 1 && half != 2) return fail(SPH_E_ARG, "half must be 1 or 2");
     hipStream_t s = as_stream(stream);
     if (half == 1) {
@@ -668,6 +757,13 @@ sph_status sph_step_batched(sph_ctx *c, int32_t n_steps, void *stream)
     if (!c->bound || !c->primed) return fail(SPH_E_STATE, "sph_bind and sph_prime first");
     if (c->cells_built) return fail(SPH_E_STATE, "a staged step is half done");
     hipStream_t s = as_stream(stream);
+    if (c->dual) {
+        for (int32_t it = 0; it < n_steps; ++it) {
+            TRY(dual_advection_step(c, s, c->timing));
+            c->steps_done += 1;
+        }
+        return SPH_OK;
+    }
     const bool graph = c->p.use_graph && !c->timing;
     for (int32_t it = 0; it < n_steps; ++it) {
         const bool ro = reorder_due(c);
@@ -679,6 +775,17 @@ sph_status sph_step_batched(sph_ctx *c, int32_t n_steps, void *stream)
         }
         c->steps_done += 1;
     }
+    return SPH_OK;
+}
+
+sph_status sph_substeps(sph_ctx *c, int32_t *n, void *stream)
+{
+    if (!c || !n) return fail(SPH_E_ARG, "null argument");
+    if (!c->dual) return fail(SPH_E_UNSUPPORTED, "sub-steps belong to the dual scheme");
+    if (!c->bound || !c->primed) return fail(SPH_E_STATE, "sph_bind and sph_prime first");
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(hipMemcpyAsync(n, c->dev.nsub, sizeof(int32_t) * c->idev.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return SPH_OK;
 }
 

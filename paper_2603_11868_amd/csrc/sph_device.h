@@ -52,11 +52,12 @@ struct InstDev {
 
 struct SimConst {
     int dim, n_inst, N, Nw, C;
-    int pad0;
+    int scheme;                        // 0 WCSPH step, 1 dual-criteria Riemann scheme
     double h, inv_h, cs, inv_cs, cut2;
     double rho0, mass, sigma0, alpha, eps_h2, cfl_ac, cfl_f;
     double kW, kF, W0;                 // W = kW t^4 (2q+1), F = kF t^3, t = 1 - q/2
     double g[3];
+    double cfl_adv, cfl_sub, eta;      // dual scheme: advection and acoustic Courant numbers, limiter
     float fh, finv_h, fcs, fcut2, fkW, fkF, feps_h2, pad1;
     float fg[3], pad2;
 };

@@ -261,28 +261,37 @@ hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kic
 // per-instance reductions -> dt, diag
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_final_reduce(SimConst sc, const InstDev *__restrict__ inst,
-                                                      const double *__restrict__ partials,
-                                                      double *__restrict__ dt,
-                                                      double *__restrict__ diag,
-                                                      int *__restrict__ clampc,
-                                                      unsigned *__restrict__ flags, int prime)
+constexpr int kReduceBlock = 1024;     // one block per instance: wide, to keep many rows in flight
+
+__global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
+    SimConst sc, const InstDev *__restrict__ inst, const double *__restrict__ partials,
+    double *__restrict__ dt, double *__restrict__ diag, int *__restrict__ clampc,
+    unsigned *__restrict__ flags, int prime, int *__restrict__ nsub, double *__restrict__ dtsub,
+    int *__restrict__ nsub_max)
 {
     const int b = blockIdx.x;
     const InstDev &I = inst[b];
-    double acc[kNPart];
-#pragma unroll
-    for (int q = 0; q < kNPart; ++q) acc[q] = 0.0;
-    // unrolled so that several rows are in flight; the per-thread order of the
-    // sums is the loop order either way
-#pragma unroll 4
-    for (int c = I.chunk_begin + threadIdx.x; c < I.chunk_end; c += blockDim.x) {
-        const double *p = partials + (int64_t)c * kNPart;
-#pragma unroll
-        for (int q = 0; q < kNPart; ++q) acc[q] = is_max_slot(q) ? fmax(acc[q], p[q]) : acc[q] + p[q];
+    // thread t sums slot t % 16 over rows t / 16, t / 16 + R, ...: a wave reads
+    // four whole 128-byte rows per load instead of 64 scattered ones
+    constexpr int R = kReduceBlock / kNPart;
+    const int q = threadIdx.x % kNPart;
+    const int r0 = threadIdx.x / kNPart;
+    const bool mx = is_max_slot(q);
+    double acc = 0.0;                      // the max slots hold non-negative values
+#pragma unroll 8
+    for (int c = I.chunk_begin + r0; c < I.chunk_end; c += R) {
+        const double x = partials[(int64_t)c * kNPart + q];
+        acc = mx ? fmax(acc, x) : acc + x;
     }
+    __shared__ double rows[R][kNPart];
     __shared__ double tot[kNPart];
-    block_partials<0, kNPart>(acc, tot);
+    rows[r0][q] = acc;
+    __syncthreads();
+    if (threadIdx.x < kNPart) {
+        double t = rows[0][q];
+        for (int r = 1; r < R; ++r) t = mx ? fmax(t, rows[r][q]) : t + rows[r][q];
+        tot[q] = t;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double *d = diag + (int64_t)b * 16;
@@ -305,9 +314,23 @@ __global__ __launch_bounds__(256) void k_final_reduce(SimConst sc, const InstDev
         d[13] += dt_used * ff;
         d[14] += dt_used;
         d[15] = prime ? 0.0 : d[15] + 1.0;
-        const double dt_ac = sc.cfl_ac * sc.h / (I.c0 + vmax);
-        const double dt_f = sc.cfl_f * sqrt(sc.h / amax);
-        dt[b] = dt_ac < dt_f ? dt_ac : dt_f;
+        if (sc.scheme == 1) {
+            // dual-criteria plan of the next advection step: Dt from the
+            // flow speed (floored at c0 / 10), equal acoustic sub-steps
+            const double uref = I.c0 / 10.0;
+            const double Dt = sc.cfl_adv * sc.h / (vmax > uref ? vmax : uref);
+            const double dac = sc.cfl_sub * sc.h / (I.c0 + vmax);
+            int ns = (int)ceil(Dt / dac);
+            ns = ns < 1 ? 1 : ns;
+            dt[b] = Dt;
+            nsub[b] = ns;
+            dtsub[b] = Dt / (double)ns;
+            atomicMax(nsub_max, ns);
+        } else {
+            const double dt_ac = sc.cfl_ac * sc.h / (I.c0 + vmax);
+            const double dt_f = sc.cfl_f * sqrt(sc.h / amax);
+            dt[b] = dt_ac < dt_f ? dt_ac : dt_f;
+        }
         if (tot[P_BAD] > 0.0) atomicOr(flags, 2u);
     }
 }
@@ -315,7 +338,8 @@ __global__ __launch_bounds__(256) void k_final_reduce(SimConst sc, const InstDev
 hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s)
 {
     if (sc.n_inst <= 0) return hipSuccess;
-    k_final_reduce<<<sc.n_inst, 256, 0, s>>>(sc, d.inst, d.partials, d.dt, d.diag, d.clampc, d.flags, prime);
+    k_final_reduce<<<sc.n_inst, kReduceBlock, 0, s>>>(sc, d.inst, d.partials, d.dt, d.diag, d.clampc, d.flags, prime,
+                                                      d.nsub, d.dtsub, d.nsub_max);
     return hipGetLastError();
 }
 

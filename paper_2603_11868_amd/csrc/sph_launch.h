@@ -43,6 +43,11 @@ struct Dev {
     int *lcount;              // [N] hits per sorted target (may exceed list_cap)
     int list_cap;             // 0: sweeps traverse the stencil (no list)
     int prefetch;             // candidate records in flight per thread (4 or 8)
+    // dual scheme
+    double *drho;             // [N] continuity rate of the last density relaxation
+    int *nsub;                // [B] acoustic sub-steps of the next advection step
+    double *dtsub;            // [B] their size
+    int *nsub_max;            // [1] max over instances
 };
 
 hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s);
@@ -67,6 +72,11 @@ hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, 
 // Staged half 2: v += dt/2 a (kick_on != 0) and the partials the force sweep
 // does not write.
 hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kick_on);
+// Dual-criteria scheme (sph_sweeps.hip): the four kernels of acoustic
+// sub-step `sub` of the current advection step; instances with fewer
+// sub-steps skip it.  list != 0: the sweeps walk the neighbour list of the
+// advection step's summation.
+hipError_t launch_dual_substep(const SimConst &sc, const Dev &d, int sub, int list, hipStream_t s, int part);
 // Per-instance reductions of the partials -> dt, diag, flags.
 hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s);
 

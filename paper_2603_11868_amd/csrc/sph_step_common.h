@@ -62,11 +62,12 @@ enum { P_VMAX = 0, P_AMAX = 1, P_MOM = 2, P_KE = 5, P_PE = 6, P_IE = 7, P_FF = 8
 
 __device__ __forceinline__ bool is_max_slot(int s) { return s == P_VMAX || s == P_AMAX; }
 
-// Reduce vals[LO..HI) over the block and write them to out[LO..HI).
-template <int LO, int HI>
+// Reduce vals[LO..HI) over the block (at most MAXW waves) and write them to
+// out[LO..HI).
+template <int LO, int HI, int MAXW = kMaxBlock / 64>
 __device__ __forceinline__ void block_partials(double (&vals)[kNPart], double *__restrict__ out)
 {
-    __shared__ double sh[kMaxBlock / 64][kNPart];
+    __shared__ double sh[MAXW][kNPart];
     const int w = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
 #pragma unroll

@@ -902,4 +902,312 @@ hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// dual-criteria scheme: acoustic sub-steps
+//
+// An advection step rebuilds the cell table, packs the sweep records at the
+// current positions and resets the density by summation (the density sweep
+// above with dt = 0); the records' positions then stay frozen for the
+// acoustic sub-steps, which relax pressure and density against that
+// configuration with interface states from the linearised Riemann problem
+// along each pair (the published scheme of the library behind the paper:
+// Zhang, Hu & Adams 2017; Zhang, Rezavand & Hu 2021).  A sub-step is
+//   first half    rho += dt/2 Drho; p = max(0, c0^2 (rho - rho0)); x += dt/2 v
+//   pressure      a_i = g - 2 m sum_j P*_ij / (rho_i rho_j) F_ij r_ij; v += dt a
+//   second half   x += dt/2 v
+//   density       Drho_i = 2 rho_i m sum_j (v_i - v*_ij).F_ij r_ij / rho_j;
+//                 rho += dt/2 Drho
+// with, along e = r_ij / |r_ij|, U_L = -v_i.e, U_R = -v_j.e, Z = rho c0,
+// beta = min(eta max(U_L - U_R, 0) / c0, 1),
+// P* = (Z_L p_R + Z_R p_L + Z_L Z_R beta (U_L - U_R)) / (Z_L + Z_R),
+// v_i - v* = Z_R (v_i - v_j) / (Z_L + Z_R) + (p_L - p_R) / (Z_L + Z_R) e,
+// and a wall j mirroring the target (rho_j = rho_i, v_j = 0,
+// p_j = max(0, p_i + rho_i g.(x_j - x_i))).  The sweeps read velocities,
+// densities and pressures from the records and write the FP64 state, so every
+// target sees the values of the start of the sweep; the per-particle kernels
+// in between refresh the records.  FP64 only.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double half_update(double y, double rate, double dt)
+{
+#pragma clang fp contract(off)
+    return y + 0.5 * dt * rate;
+}
+
+__device__ __forceinline__ double full_update(double y, double rate, double dt)
+{
+#pragma clang fp contract(off)
+    return y + dt * rate;
+}
+
+// First half (sorted order): density and pressure of the sub-step, half drift.
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_dual_first(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ perm, double *__restrict__ x, const double *__restrict__ v,
+    double *__restrict__ rho, const double *__restrict__ drho, const int *__restrict__ nsub,
+    const double *__restrict__ dtsub, int sub, typename Rec<DIM, false>::v4 *__restrict__ rec)
+{
+    using V = RV<DIM, false>;
+    const Chunk ch = map[blockIdx.x];
+    if (sub >= nsub[ch.inst]) return;
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const int n = sc.N;
+    const InstDev &I = inst[ch.inst];
+    const double dt = dtsub[ch.inst];
+    const int i = perm[k];
+    const double r = half_update(rho[i], drho[i], dt);
+    double p = I.c0 * I.c0 * (r - sc.rho0);
+    if (p < 0.0) p = 0.0;
+    rho[i] = r;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) x[(int64_t)c * n + i] = half_update(x[(int64_t)c * n + i], v[(int64_t)c * n + i], dt);
+    dvec2 rp;
+    rp.x = r;
+    rp.y = p;
+    reinterpret_cast<dvec2 *>(rec)[V::rhoP_slot(k)] = rp;
+}
+
+// Second half (sorted order): half drift with the new velocity, and the new
+// velocity into the records.
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_dual_second(
+    SimConst sc, const Chunk *__restrict__ map, const int *__restrict__ perm, double *__restrict__ x,
+    const double *__restrict__ v, const int *__restrict__ nsub, const double *__restrict__ dtsub, int sub,
+    typename Rec<DIM, false>::v4 *__restrict__ rec)
+{
+    const Chunk ch = map[blockIdx.x];
+    if (sub >= nsub[ch.inst]) return;
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const int n = sc.N;
+    const double dt = dtsub[ch.inst];
+    const int i = perm[k];
+    double vi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        vi[c] = v[(int64_t)c * n + i];
+        x[(int64_t)c * n + i] = half_update(x[(int64_t)c * n + i], vi[c], dt);
+    }
+    double *A = reinterpret_cast<double *>(rec + 2 * (int64_t)k);
+    if constexpr (DIM == 3) {
+        A[3] = vi[0];                      // A.w
+        A[4] = vi[1];                      // B.x
+        A[5] = vi[2];                      // B.y
+    } else {
+        A[2] = vi[0];                      // A.z
+        A[3] = vi[1];                      // A.w
+    }
+}
+
+// Pair state shared by both sweeps.
+template <int DIM>
+struct DualPair {
+    double e[3], ul, ur, rho_j, p_j, vj[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ void dual_pair(const SimConst &sc, bool wall, const double *r, double r2,
+                                          const double *vi, double rho_i, double p_i,
+                                          const typename RV<DIM, false>::v4 &Aj,
+                                          const typename RV<DIM, false>::v4 &Bj, DualPair<DIM> &q)
+{
+    using V = RV<DIM, false>;
+    V::vel(Aj, Bj, q.vj);                  // zero for walls
+    double gr = sc.g[0] * r[0] + sc.g[1] * r[1];
+    if constexpr (DIM == 3) gr += sc.g[2] * r[2];
+    double p_m = p_i - rho_i * gr;         // wall mirror: p_i + rho_i g.(x_j - x_i)
+    p_m = p_m < 0.0 ? 0.0 : p_m;
+    q.rho_j = wall ? rho_i : V::rho(Bj);
+    q.p_j = wall ? p_m : V::P(Bj);
+    const double rr = sqrt(r2);
+    const double inv = rr > 0.0 ? 1.0 / rr : 0.0;
+    q.ul = 0.0;
+    q.ur = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        q.e[c] = r[c] * inv;
+        q.ul -= vi[c] * q.e[c];
+        q.ur -= q.vj[c] * q.e[c];
+    }
+}
+
+// Pressure relaxation (sorted order): a and v of the FP64 state; the
+// fluid-fluid force and pair counts go to the per-chunk partials.
+template <int DIM, int LIST>
+__global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
+    const int *__restrict__ wstart, const typename Rec<DIM, false>::v4 *__restrict__ rec,
+    const typename Rec<DIM, false>::wpos_t *__restrict__ wpos, double *__restrict__ a,
+    double *__restrict__ v, const int *__restrict__ nsub, const double *__restrict__ dtsub, int sub,
+    double *__restrict__ partials, const uint4 *__restrict__ nlist, const int *__restrict__ lcount, int cap)
+{
+    using V = RV<DIM, false>;
+    using v4 = typename V::v4;
+    const Chunk ch = map[blockIdx.x];
+    if (sub >= nsub[ch.inst]) return;      // uniform over the block
+    const int k = ch.begin + threadIdx.x;
+    const bool act = k < ch.end;
+    const int n = sc.N;
+    const InstDev &I = inst[ch.inst];
+    const int kk = act ? k : ch.begin;
+    const v4 Ai = V::loadA(rec, kk);
+    const v4 Bi = V::loadB(rec, kk);
+    double pi[3], vi[3];
+    V::pos(Ai, pi);
+    V::vel(Ai, Bi, vi);
+    const double rho_i = V::rho(Bi), p_i = V::P(Bi);
+    const double c0 = I.c0;
+    double acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
+    int cnt = 0;
+    auto pair = [&](bool wall, int, const double *r, double r2, const v4 &Aj, const v4 &Bj)
+        __attribute__((always_inline)) {
+        DualPair<DIM> q;
+        dual_pair<DIM>(sc, wall, r, r2, vi, rho_i, p_i, Aj, Bj, q);
+        const double zl = rho_i * c0, zr = q.rho_j * c0;
+        const double du = q.ul - q.ur;
+        double beta = sc.eta * (du > 0.0 ? du : 0.0) / c0;
+        beta = beta > 1.0 ? 1.0 : beta;
+        const double ps = (zl * q.p_j + zr * p_i + zl * zr * beta * du) / (zl + zr);
+        double F;
+        kernel_F(r2, sc.inv_h, sc.kF, F);
+        const double coef = 2.0 * ps / (rho_i * q.rho_j) * F;
+        const double coef_ff = wall ? 0.0 : coef;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            acc[c] -= coef * r[c];
+            aff[c] -= coef_ff * r[c];
+        }
+        ++cnt;
+    };
+    if (act) {
+        const int lk = skey[k] - I.cell_base;
+        if constexpr (LIST) {
+            const int m = lcount[k];
+            if (m <= cap) walk_list<DIM, false, 4, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+            else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        } else {
+            for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        }
+    }
+    double vals[kNPart];
+#pragma unroll
+    for (int q = 0; q < kNPart; ++q) vals[q] = 0.0;
+    if (act) {
+        const int i = perm[k];
+        const double dt = dtsub[ch.inst];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const double an = sc.g[c] + sc.mass * acc[c];
+            a[(int64_t)c * n + i] = an;
+            v[(int64_t)c * n + i] = full_update(v[(int64_t)c * n + i], an, dt);
+            vals[P_FF + c] = sc.mass * (sc.mass * aff[c]);
+        }
+        vals[P_PAIRS] = (double)cnt;
+    }
+    block_partials<P_FF, P_PAIRS + 1>(vals, partials + (int64_t)ch.id * kNPart);
+}
+
+// Density relaxation (sorted order): Drho and rho of the FP64 state.
+template <int DIM, int LIST>
+__global__ __launch_bounds__(kMaxBlock) void k_dual_density(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
+    const int *__restrict__ wstart, const typename Rec<DIM, false>::v4 *__restrict__ rec,
+    const typename Rec<DIM, false>::wpos_t *__restrict__ wpos, double *__restrict__ rho,
+    double *__restrict__ drho, const int *__restrict__ nsub, const double *__restrict__ dtsub, int sub,
+    const uint4 *__restrict__ nlist, const int *__restrict__ lcount, int cap)
+{
+    using V = RV<DIM, false>;
+    using v4 = typename V::v4;
+    const Chunk ch = map[blockIdx.x];
+    if (sub >= nsub[ch.inst]) return;
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const int n = sc.N;
+    const InstDev &I = inst[ch.inst];
+    const v4 Ai = V::loadA(rec, k);
+    const v4 Bi = V::loadB(rec, k);
+    double pi[3], vi[3];
+    V::pos(Ai, pi);
+    V::vel(Ai, Bi, vi);
+    const double rho_i = V::rho(Bi), p_i = V::P(Bi);
+    const double c0 = I.c0;
+    double sum = 0.0;
+    auto pair = [&](bool wall, int, const double *r, double r2, const v4 &Aj, const v4 &Bj)
+        __attribute__((always_inline)) {
+        DualPair<DIM> q;
+        dual_pair<DIM>(sc, wall, r, r2, vi, rho_i, p_i, Aj, Bj, q);
+        const double zl = rho_i * c0, zr = q.rho_j * c0, zs = zl + zr;
+        double dot = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const double dv = zr * (vi[c] - q.vj[c]) / zs + (p_i - q.p_j) / zs * q.e[c];
+            dot += dv * r[c];
+        }
+        double F;
+        kernel_F(r2, sc.inv_h, sc.kF, F);
+        sum += dot * F / q.rho_j;
+    };
+    const int lk = skey[k] - I.cell_base;
+    if constexpr (LIST) {
+        const int m = lcount[k];
+        if (m <= cap) walk_list<DIM, false, 4, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+        else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+    } else {
+        for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+    }
+    const int i = perm[k];
+    const double d = 2.0 * rho_i * (sc.mass * sum);
+    drho[i] = d;
+    rho[i] = half_update(rho[i], d, dtsub[ch.inst]);
+}
+
+template <int DIM>
+static void dual_dispatch(const SimConst &sc, const Dev &d, int sub, int list, hipStream_t s, int part)
+{
+    using R = Rec<DIM, false>;
+    auto *rec = static_cast<typename R::v4 *>(d.rec);
+    auto *wpos = static_cast<const typename R::wpos_t *>(d.wpos);
+    switch (part) {
+    case 0:
+        k_dual_first<DIM><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.inst, d.perm, d.x, d.v, d.rho, d.drho,
+                                                         d.nsub, d.dtsub, sub, rec);
+        break;
+    case 1:
+        if (list)
+            k_dual_pressure<DIM, 1><<<d.nfchunks, d.block, 0, s>>>(
+                sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.a, d.v, d.nsub,
+                d.dtsub, sub, d.partials, d.nlist, d.lcount, d.list_cap);
+        else
+            k_dual_pressure<DIM, 0><<<d.nfchunks, d.block, 0, s>>>(
+                sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.a, d.v, d.nsub,
+                d.dtsub, sub, d.partials, d.nlist, d.lcount, d.list_cap);
+        break;
+    case 2:
+        k_dual_second<DIM><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.perm, d.x, d.v, d.nsub, d.dtsub, sub, rec);
+        break;
+    default:
+        if (list)
+            k_dual_density<DIM, 1><<<d.nfchunks, d.block, 0, s>>>(
+                sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.rho, d.drho, d.nsub,
+                d.dtsub, sub, d.nlist, d.lcount, d.list_cap);
+        else
+            k_dual_density<DIM, 0><<<d.nfchunks, d.block, 0, s>>>(
+                sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.rho, d.drho, d.nsub,
+                d.dtsub, sub, d.nlist, d.lcount, d.list_cap);
+        break;
+    }
+}
+
+hipError_t launch_dual_substep(const SimConst &sc, const Dev &d, int sub, int list, hipStream_t s, int part)
+{
+    if (d.nfchunks <= 0) return hipSuccess;
+    if (sc.dim == 2) dual_dispatch<2>(sc, d, sub, list, s, part);
+    else dual_dispatch<3>(sc, d, sub, list, s, part);
+    return hipGetLastError();
+}
+
 }  // namespace sphx

@@ -36,7 +36,12 @@ SYMBOLS = ("sph_last_error", "sph_create", "sph_destroy", "sph_get_info", "sph_g
            "sph_workspace_size", "sph_bind", "sph_prime", "sph_build_cells", "sph_sort",
            "sph_density", "sph_forces", "sph_integrate", "sph_step_batched",
            "sph_poll_errors", "sph_set_timing", "sph_stage_times", "sph_stage_name",
-           "sph_stage_count")
+           "sph_stage_count", "sph_substeps")
+
+SPH_SCHEME_WCSPH, SPH_SCHEME_DUAL = 0, 1
+# parameters of the dual-criteria scheme as published (advection and acoustic
+# Courant numbers, dissipation limiter slope)
+DUAL_CFL_ADV, DUAL_CFL_AC, DUAL_ETA = 0.25, 0.6, 3.0
 
 
 class SphError(RuntimeError):
@@ -57,7 +62,8 @@ class sph_params(C.Structure):
                 ("cfl_ac", C.c_double), ("cfl_f", C.c_double), ("g", C.c_double * 3),
                 ("inst", C.POINTER(sph_instance_desc)), ("block_threads", C.c_int32),
                 ("use_graph", C.c_int32), ("list_cap", C.c_int32),
-                ("prefetch", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("prefetch", C.c_int32), ("scheme", C.c_int32), ("reserved0", C.c_int32),
+                ("cfl_adv", C.c_double), ("eta", C.c_double), ("reserved", C.c_int32 * 4)]
 
 
 class sph_buffers(C.Structure):
@@ -100,6 +106,7 @@ def lib():
         L.sph_sort.argtypes = [vp, C.c_int32, vp]
         L.sph_integrate.argtypes = [vp, C.c_int32, vp]
         L.sph_step_batched.argtypes = [vp, C.c_int32, vp]
+        L.sph_substeps.argtypes = [vp, C.POINTER(C.c_int32), vp]
         L.sph_poll_errors.argtypes = [vp, C.POINTER(C.c_uint32), vp]
         L.sph_set_timing.argtypes = [vp, C.c_int32]
         L.sph_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32,
@@ -197,6 +204,12 @@ def sph_step_batched(ctx, n_steps, stream=None):
     _check(lib().sph_step_batched(ctx, int(n_steps), _stream(stream)))
 
 
+def sph_substeps(ctx, n_instances, stream=None):
+    out = (C.c_int32 * n_instances)()
+    _check(lib().sph_substeps(ctx, out, _stream(stream)))
+    return [int(v) for v in out]
+
+
 def sph_poll_errors(ctx, stream=None) -> int:
     f = C.c_uint32()
     _check(lib().sph_poll_errors(ctx, C.byref(f), _stream(stream)))
@@ -234,7 +247,8 @@ class Simulation:
 
     def __init__(self, case, precision="fp64", reorder_every=None, block_threads=0,
                  use_graph=False, device="cuda", alpha=None, g=None,
-                 cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0):
+                 cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0,
+                 scheme="wcsph"):
         import torch
         self.torch = torch
         self.case = case
@@ -268,6 +282,13 @@ class Simulation:
         p.use_graph = int(bool(use_graph))
         p.list_cap = int(list_cap)
         p.prefetch = int(prefetch)
+        if scheme == "dual":
+            p.scheme = SPH_SCHEME_DUAL
+            p.cfl_ac = DUAL_CFL_AC if cfl is None else float(cfl)
+            p.cfl_adv, p.eta = DUAL_CFL_ADV, DUAL_ETA
+        elif scheme != "wcsph":
+            raise ValueError(f"unknown scheme {scheme!r}")
+        self.scheme = scheme
         self._descs = descs
         self.params = p
         self.precision = precision

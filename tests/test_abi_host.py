@@ -137,3 +137,17 @@ def test_product_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sph, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         sph.lib()
+
+
+def test_dual_scheme_options_are_checked(sphmod):
+    case = dambreak.make_case("tiny_2d")
+    base = dict(scheme=sphmod.SPH_SCHEME_DUAL, cfl_ac=sphmod.DUAL_CFL_AC,
+                cfl_adv=sphmod.DUAL_CFL_ADV, eta=sphmod.DUAL_ETA)
+    p, descs = _params(sphmod, case, **base)
+    ctx = sphmod.sph_create(p)
+    sphmod.sph_destroy(ctx)
+    for over, status in ((dict(precision=1), "UNSUPPORTED"), (dict(use_graph=1), "UNSUPPORTED"),
+                         (dict(cfl_adv=0.0), "E_ARG"), (dict(scheme=7), "E_ARG")):
+        p, descs = _params(sphmod, case, **dict(base, **over))
+        with pytest.raises(sphmod.SphError, match=status):
+            sphmod.sph_create(p)

@@ -1,0 +1,136 @@
+"""Parity of the dual-criteria Riemann scheme on the GPU (through the C ABI)
+with the FP64 CPU reference: integers bit for bit, fields to the tolerances
+written in each test, the sub-step plan exactly."""
+import numpy as np
+import pytest
+
+import dambreak
+from _parity import errors, gpu_instance_view, integer_mismatches, oracle_view, oracles_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(case, **kw):
+    from paper_2603_11868_amd import sph
+    return sph.Simulation(case, scheme="dual", **kw)
+
+
+def _check_integers(g, r, what):
+    mm = integer_mismatches(g, r)
+    assert all(v == 0 for v in mm.values()), f"{what}: integer mismatches {mm}"
+
+
+def _refs(case):
+    refs = oracles_for(case)
+    for r in refs:
+        r.dual_prime()
+    return refs
+
+
+@pytest.mark.parametrize("name", ["tiny_2d", "c1_2d", "tiny_3d", "small_batch"])
+def test_prime_parity(name):
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case(name)
+    sim = _sim(case)
+    refs = _refs(case)
+    sim.prime()
+    h = sim.host()
+    assert sim.poll_errors() == 0
+    nsub = sph.sph_substeps(sim.ctx, sim.B)
+    for b, r in enumerate(refs):
+        g = gpu_instance_view(sim, h, b)
+        rv = oracle_view(r)
+        _check_integers(g, rv, f"{name}[{b}] prime")
+        assert np.abs(g["rho"] - rv["rho"]).max() <= 1e-13 * case.rho0
+        assert np.abs(g["a"] - rv["a"]).max() <= 1e-10 * np.abs(rv["a"]).max()
+        Dt, n, _ = r.dual_plan()
+        assert g["dt"] == pytest.approx(Dt, rel=1e-14)
+        assert nsub[b] == n
+    sim.close()
+
+
+@pytest.mark.parametrize("name,tol1,tol20", [("c1_2d", 1e-9, 1e-6), ("tiny_3d", 1e-9, 1e-6),
+                                             ("small_batch", 1e-9, 1e-6)])
+def test_advection_steps_parity(name, tol1, tol20):
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case(name)
+    sim = _sim(case)
+    refs = _refs(case)
+    sim.prime()
+    for n_done, tol in ((1, tol1), (20, tol20)):
+        sim.step(n_done - sim.steps_done)
+        for r in refs:
+            r.dual_step(n_done - r.step_count)
+        h = sim.host()
+        assert sim.poll_errors() == 0
+        nsub = sph.sph_substeps(sim.ctx, sim.B)
+        for b, r in enumerate(refs):
+            g = gpu_instance_view(sim, h, b)
+            rv = oracle_view(r)
+            e = errors(g, rv, case.instances[b].fluid)
+            print(name, b, n_done, e)
+            assert max(e["rho"], e["v"], e["x"]) < 1e-5, e
+            assert max(e["rho"], e["v"], e["x_beyond_rounding"], e["dt"]) < tol, (b, n_done, e)
+            _check_integers(g, rv, f"{name}[{b}] step {n_done}")
+            assert nsub[b] == r.dual_plan()[1]
+            # simulated time: the sum of the advection steps taken
+            assert g["diag"][14] == pytest.approx(rv["diag"][14], rel=1e-12)
+    sim.close()
+
+
+def test_batch_equals_instances_alone():
+    case = dambreak.make_case("small_batch")
+    sim = _sim(case)
+    sim.prime()
+    sim.step(6)
+    h = sim.host()
+    for b, inst in enumerate(case.instances):
+        single = dambreak.Case(case.name, case.dim, case.dx, case.h,
+                               reorder_every=case.reorder_every, instances=[inst])
+        s1 = _sim(single)
+        s1.prime()
+        s1.step(6)
+        h1 = s1.host()
+        g = gpu_instance_view(sim, h, b)
+        g1 = gpu_instance_view(s1, h1, 0)
+        for k in ("key", "perm", "sorted_ids", "count", "x", "v", "a", "rho"):
+            assert np.array_equal(g[k], g1[k]), (b, k)
+        assert g["dt"] == g1["dt"]
+        s1.close()
+    sim.close()
+
+
+def test_list_and_direct_search_agree_and_reruns_are_identical():
+    case = dambreak.make_case("tiny_3d")
+    runs = []
+    for kw in (dict(), dict(), dict(list_cap=-1), dict(list_cap=8)):
+        s = _sim(case, **kw)
+        s.prime()
+        s.step(5)
+        flags = s.poll_errors()
+        runs.append((s.host(), flags))
+        s.close()
+    (h0, f0), (h1, _), (h2, _), (h3, f3) = runs
+    assert f0 == 0
+    for k in ("x", "v", "a", "rho", "count", "perm", "dt"):
+        assert np.array_equal(h0[k], h1[k]), k
+    for other in (h2, h3):
+        for k in ("id", "key", "perm", "cell_start", "count"):
+            assert np.array_equal(h0[k], other[k]), k
+        for k in ("x", "v", "a", "rho", "dt"):
+            scale = max(np.abs(h0[k]).max(), 1e-300)
+            assert np.abs(other[k] - h0[k]).max() <= 1e-12 * scale, k
+
+
+def test_stage_calls_are_refused():
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case("tiny_2d")
+    s = _sim(case)
+    s.prime()
+    for call in (lambda: sph.sph_build_cells(s.ctx), lambda: sph.sph_density(s.ctx),
+                 lambda: sph.sph_forces(s.ctx), lambda: sph.sph_integrate(s.ctx, 2)):
+        with pytest.raises(sph.SphError, match="UNSUPPORTED"):
+            call()
+    s.step(1)
+    assert s.poll_errors() == 0
+    s.close()
