@@ -40,6 +40,16 @@ FLOPS = {
     2: {"cand": 5, "density": 20, "force": 24},
     3: {"cand": 8, "density": 23, "force": 30},
 }
+# dual-criteria scheme, FP64 flops per neighbour pair of a sub-step sweep.
+# Both sweeps: unit vector and normal velocities (sqrt, division, 2 dot
+# products), the limiter and the Riemann state (about 12), the kernel
+# gradient factor (sqrt, q, t, t^3, F).  Pressure: P*/(rho_i rho_j) F and the
+# vector accumulation.  Density: the velocity jump, its dot product with r and
+# the accumulation.
+FLOPS_DUAL = {
+    2: {"sub_pressure": 37, "sub_density": 41},
+    3: {"sub_pressure": 45, "sub_density": 51},
+}
 
 WORKLOADS = {
     "c2_3d": "3D WCSPH dam break: 1x1x2 m fluid block at dx=0.01 (2,000,000 fluid + "
@@ -115,16 +125,18 @@ def load_traffic(workload, precision, kernel):
 
 
 def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
-            list_cap=0, prefetch=0, stage_steps=0):
+            list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph"):
     import torch
     from paper_2603_11868_amd import sph
 
     sim = sph.Simulation(case, precision=precision, reorder_every=reorder_every,
                          use_graph=graph, block_threads=block,
-                         list_cap=list_cap, prefetch=prefetch)
+                         list_cap=list_cap, prefetch=prefetch, scheme=scheme)
     sim.prime()
     sim.step(warmup)
     torch.cuda.synchronize()
+    sub0 = int(sph.sph_get_info(sim.ctx).substeps_done)
+    tsim0 = sim.host()["diag"][:, 14].copy()
     if timing:
         sph.sph_set_timing(sim.ctx, 1)
         sph.sph_stage_times(sim.ctx, reset=True)
@@ -133,6 +145,8 @@ def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, b
     sim.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    tsim1 = sim.host()["diag"][:, 14].copy()
+    sub1 = int(sph.sph_get_info(sim.ctx).substeps_done)
     stages = sph.sph_stage_times(sim.ctx, reset=True) if timing else {}
     sph.sph_set_timing(sim.ctx, 0)
     if graph and stage_steps:
@@ -146,13 +160,27 @@ def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, b
         sph.sph_set_timing(sim.ctx, 0)
     flags = sim.poll_errors()
     h = sim.host()
+    sim.timed_substeps = sub1 - sub0
+    # simulated seconds advanced in the timed region (mean over instances)
+    sim.timed_sim_time = float(np.mean(tsim1 - tsim0))
     return sim, h, t1 - t0, stages, flags
 
 
-def cpu_baseline(case, nsteps):
+def cpu_baseline(case, nsteps, scheme="wcsph"):
+    """The CPU reference on the same workload: M updates/s over nsteps steps
+    (dual scheme: advection steps, counted in acoustic sub-steps)."""
     from oracle import oracle as O
 
     ref = O.OracleSim.from_case(case)
+    if scheme == "dual":
+        ref.dual_prime()
+        t0 = time.perf_counter()
+        subs = 0
+        for _ in range(nsteps):
+            subs += ref.dual_plan()[1]
+            ref.dual_step(1)
+        t1 = time.perf_counter()
+        return ref, case.n_fluid * subs / (t1 - t0) / 1e6, O.num_threads(), t1 - t0
     ref.prime()
     t0 = time.perf_counter()
     ref.step(nsteps)
@@ -167,6 +195,9 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--case", default="c2_3d", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--scheme", default="wcsph", choices=("wcsph", "dual"),
+                    help="dual: dual-criteria Riemann scheme (steps are advection steps, "
+                         "updates are acoustic sub-steps)")
     ap.add_argument("--compare", default="mixed", choices=("mixed", "fp64", "none"),
                     help="second precision timed on the same workload")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
@@ -208,8 +239,10 @@ def main(argv=None):
                                           stage_steps=min(args.steps, 50),
                                           reorder_every=args.reorder_every, block=args.block,
                                           list_cap=args.list,
-                                          prefetch=args.prefetch)
-    value = n_fluid * args.steps / secs / 1e6
+                                          prefetch=args.prefetch, scheme=args.scheme)
+    updates = sim.timed_substeps if args.scheme == "dual" else args.steps
+    sim_time = sim.timed_sim_time
+    value = n_fluid * updates / secs / 1e6
     log(f"{args.precision}: {secs * 1e3 / args.steps:.3f} ms/step, {value:.1f} M updates/s, flags {flags}")
     for k, (ms, n) in stages.items():
         if n:
@@ -223,7 +256,16 @@ def main(argv=None):
         dim = case.dim
         pairs = float(h["diag"][:, 12].sum())
         cands = candidate_count(sim, h)
-        if name in ("density", "force"):
+        if name in ("sub_pressure", "sub_density"):
+            # a sub-step sweep walks the pairs of the advection step's list
+            flops = FLOPS_DUAL[dim][name] * pairs
+            achieved = flops / avg_s / 1e12
+            roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
+                    "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
+                    "traffic": load_traffic(args.case, "dual", name), "flops_per_launch": float(flops),
+                    "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
+        elif name in ("density", "force"):
             flops = FLOPS[dim]["cand"] * cands + FLOPS[dim][name] * pairs
             achieved = flops / avg_s / 1e12
             traffic = load_traffic(args.case, args.precision, name)
@@ -244,6 +286,8 @@ def main(argv=None):
     torch.cuda.empty_cache()
 
     other = None
+    if args.scheme == "dual":
+        args.compare = "none"          # the dual scheme runs in FP64 only
     if args.compare != "none" and args.compare != args.precision:
         sim2, h2, secs2, stages2, flags2 = run_gpu(case, args.compare, args.steps, args.warmup,
                                                    args.graph, timing=not args.graph,
@@ -280,14 +324,19 @@ def main(argv=None):
 
     cpu = None
     if args.cpu_steps > 0:
-        _, cv, cores, csecs = cpu_baseline(case, args.cpu_steps)
+        _, cv, cores, csecs = cpu_baseline(case, args.cpu_steps, args.scheme)
+        what = "advection steps (their acoustic sub-steps counted)" if args.scheme == "dual" else "full steps"
         cpu = {"value": round(cv, 4), "unit": "M particle-updates/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{args.case}: FP64 CPU reference, prime + {args.cpu_steps} full "
-                         f"steps of all {n_fluid} fluid particles ({csecs:.1f} s)"}
+               "sample": f"{args.case}: FP64 CPU reference, prime + {args.cpu_steps} {what} "
+                         f"of all {n_fluid} fluid particles ({csecs:.1f} s)"}
         log(f"cpu oracle: {cv:.3f} M updates/s on {cores} threads ({csecs:.1f} s)")
 
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
+    extra = {"sim_seconds_per_second": (round(sim_time / secs, 6) if sim_time else None)}
+    if args.scheme == "dual":
+        # one update = one acoustic sub-step of one fluid particle
+        extra["substeps"] = int(updates)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "M particle-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -298,9 +347,9 @@ def main(argv=None):
                    "reorder_every": case.reorder_every if args.reorder_every is None else args.reorder_every,
                    "graph": bool(args.graph), "block_threads": args.block or 256,
                    "list_cap": args.list,
-                   "prefetch": args.prefetch or 8},
+                   "prefetch": args.prefetch or 8, "scheme": args.scheme},
         "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
-        "compare": other, "flags": int(flags),
+        "compare": other, "flags": int(flags), **extra,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -172,6 +172,9 @@ typedef struct {
     double mass;             /* particle mass rho0/sigma0 */
     double cell_size;        /* 2h */
     int64_t steps_done;      /* steps since sph_prime */
+    int64_t substeps_done;   /* SPH_SCHEME_DUAL: acoustic sub-steps since
+                                sph_prime (per step, the largest count over
+                                the instances) */
 } sph_info;
 
 typedef struct sph_ctx sph_ctx;

@@ -106,6 +106,7 @@ struct sph_ctx {
     sph_buffers buf{};
     Dev dev{};
     int64_t steps_done = 0;
+    int64_t substeps_done = 0;   // dual scheme: sub-step loop iterations
     // graphs
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -384,6 +385,7 @@ sph_status dual_advection_step(sph_ctx *c, hipStream_t s, bool timed)
     TRY(check_launch(launch_fill_f64(d.drho, c->N, 0.0, s), "fill"));
     for (int sub = 0; sub < nmax; ++sub)
         for (int part = 0; part < 4; ++part) TRY(do_dual_part(c, sub, part, s, timed));
+    c->substeps_done += nmax;
     return dual_reduce(c, 0, s, timed);
 }
 
@@ -572,6 +574,7 @@ sph_status sph_get_info(const sph_ctx *ctx, sph_info *info)
     info->mass = ctx->sc.mass;
     info->cell_size = ctx->sc.cs;
     info->steps_done = ctx->steps_done;
+    info->substeps_done = ctx->substeps_done;
     return SPH_OK;
 }
 
@@ -666,6 +669,7 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     c->cells_built = false;
     c->list_valid = false;
     c->steps_done = 0;
+    c->substeps_done = 0;
     return SPH_OK;
 }
 
@@ -690,6 +694,7 @@ sph_status sph_prime(sph_ctx *c, void *stream)
     c->primed = true;
     c->cells_built = false;
     c->steps_done = 0;
+    c->substeps_done = 0;
     return SPH_OK;
 }
 

@@ -77,7 +77,7 @@ class sph_buffers(C.Structure):
 class sph_info(C.Structure):
     _fields_ = [("n_fluid", C.c_int64), ("n_wall", C.c_int64), ("n_cells", C.c_int64),
                 ("workspace_bytes", C.c_size_t), ("sigma0", C.c_double), ("mass", C.c_double),
-                ("cell_size", C.c_double), ("steps_done", C.c_int64)]
+                ("cell_size", C.c_double), ("steps_done", C.c_int64), ("substeps_done", C.c_int64)]
 
 
 _lib = None

@@ -134,3 +134,27 @@ def test_stage_calls_are_refused():
     s.step(1)
     assert s.poll_errors() == 0
     s.close()
+
+
+@pytest.mark.slow
+def test_full_size_c2_one_advection_step():
+    """The 2.0 M-particle 3D workload: prime and one advection step (its
+    acoustic sub-steps included) against the reference, every particle."""
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case("c2_3d")
+    sim = _sim(case)
+    (r,) = _refs(case)
+    sim.prime()
+    assert sph.sph_substeps(sim.ctx, 1)[0] == r.dual_plan()[1]
+    sim.step(1)
+    r.dual_step(1)
+    assert sim.poll_errors() == 0
+    h = sim.host()
+    g = gpu_instance_view(sim, h, 0)
+    rv = oracle_view(r)
+    e = errors(g, rv, case.instances[0].fluid)
+    print("c2 dual 1 step", e)
+    assert max(e["rho"], e["v"], e["x"]) < 1e-5, e
+    assert max(e["rho"], e["v"], e["x_beyond_rounding"], e["dt"]) < 1e-9, e
+    _check_integers(g, rv, "c2 dual step 1")
+    sim.close()
