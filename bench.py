@@ -125,17 +125,19 @@ def load_traffic(workload, precision, kernel):
 
 
 def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
-            list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph"):
+            list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph", skin_h=0.0):
     import torch
     from paper_2603_11868_amd import sph
 
     sim = sph.Simulation(case, precision=precision, reorder_every=reorder_every,
                          use_graph=graph, block_threads=block,
-                         list_cap=list_cap, prefetch=prefetch, scheme=scheme)
+                         list_cap=list_cap, prefetch=prefetch, scheme=scheme,
+                         skin=skin_h * case.h)
     sim.prime()
     sim.step(warmup)
     torch.cuda.synchronize()
     sub0 = int(sph.sph_get_info(sim.ctx).substeps_done)
+    builds0 = sim.cell_builds()
     tsim0 = sim.host()["diag"][:, 14].copy()
     if timing:
         sph.sph_set_timing(sim.ctx, 1)
@@ -147,6 +149,7 @@ def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, b
     t1 = time.perf_counter()
     tsim1 = sim.host()["diag"][:, 14].copy()
     sub1 = int(sph.sph_get_info(sim.ctx).substeps_done)
+    sim.timed_builds = sim.cell_builds() - builds0
     stages = sph.sph_stage_times(sim.ctx, reset=True) if timing else {}
     sph.sph_set_timing(sim.ctx, 0)
     if graph and stage_steps:
@@ -205,6 +208,8 @@ def main(argv=None):
     ap.add_argument("--list", type=int, default=0, help="neighbour-list capacity (-1: no list)")
     ap.add_argument("--prefetch", type=int, default=0, help="candidate records in flight (4 or 8)")
     ap.add_argument("--reorder-every", type=int, default=None)
+    ap.add_argument("--skin", type=float, default=0.0,
+                    help="Verlet skin in units of h (0: cells and lists rebuilt every step)")
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps of the CPU sample (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (PMC calibration)")
@@ -239,7 +244,8 @@ def main(argv=None):
                                           stage_steps=min(args.steps, 50),
                                           reorder_every=args.reorder_every, block=args.block,
                                           list_cap=args.list,
-                                          prefetch=args.prefetch, scheme=args.scheme)
+                                          prefetch=args.prefetch, scheme=args.scheme,
+                                          skin_h=args.skin)
     updates = sim.timed_substeps if args.scheme == "dual" else args.steps
     sim_time = sim.timed_sim_time
     value = n_fluid * updates / secs / 1e6
@@ -266,9 +272,11 @@ def main(argv=None):
                     "traffic": load_traffic(args.case, "dual", name), "flops_per_launch": float(flops),
                     "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
         elif name in ("density", "force"):
-            flops = FLOPS[dim]["cand"] * cands + FLOPS[dim][name] * pairs
+            # with a skin the candidates are tested at builds only
+            build_frac = sim.timed_builds / args.steps
+            flops = FLOPS[dim]["cand"] * cands * build_frac + FLOPS[dim][name] * pairs
             achieved = flops / avg_s / 1e12
-            traffic = load_traffic(args.case, args.precision, name)
+            traffic = load_traffic(args.case, args.precision + ("_skin" if args.skin else ""), name)
             roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
@@ -281,6 +289,7 @@ def main(argv=None):
                     "unit": "GB/s", "frac": None, "traffic": None, "avg_ms": round(avg_s * 1e3, 4)}
     stage_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages.items() if n}
     state_fp = {"x": h["x"], "v": h["v"], "rho": h["rho"], "id": h["id"]}
+    timed_builds = sim.timed_builds
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -294,7 +303,8 @@ def main(argv=None):
                                                    stage_steps=min(args.steps, 50),
                                                    reorder_every=args.reorder_every,
                                                    block=args.block,
-                                                   list_cap=args.list, prefetch=args.prefetch)
+                                                   list_cap=args.list, prefetch=args.prefetch,
+                                                   skin_h=args.skin)
         v2 = n_fluid * args.steps / secs2 / 1e6
         # difference between the two precisions after the same steps, by particle id
         def by_id(st):
@@ -333,7 +343,8 @@ def main(argv=None):
         log(f"cpu oracle: {cv:.3f} M updates/s on {cores} threads ({csecs:.1f} s)")
 
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
-    extra = {"sim_seconds_per_second": (round(sim_time / secs, 6) if sim_time else None)}
+    extra = {"sim_seconds_per_second": (round(sim_time / secs, 6) if sim_time else None),
+             "cell_builds": int(timed_builds)}
     if args.scheme == "dual":
         # one update = one acoustic sub-step of one fluid particle
         extra["substeps"] = int(updates)
@@ -347,7 +358,8 @@ def main(argv=None):
                    "reorder_every": case.reorder_every if args.reorder_every is None else args.reorder_every,
                    "graph": bool(args.graph), "block_threads": args.block or 256,
                    "list_cap": args.list,
-                   "prefetch": args.prefetch or 8, "scheme": args.scheme},
+                   "prefetch": args.prefetch or 8, "scheme": args.scheme,
+                   "skin_h": args.skin},
         "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
         "compare": other, "flags": int(flags), **extra,
     }

@@ -104,9 +104,10 @@ typedef struct {
     int32_t n_instances;     /* >= 1 */
     int32_t reorder_every;   /* K: physical reorder of the arrays by cell every K
                                 steps (0 = never); the cell table itself is
-                                rebuilt every step */
+                                rebuilt every step (with a skin: on a rebuild
+                                at least K steps after the last reorder) */
     double dx;               /* lattice spacing of the initial particles */
-    double h;                /* smoothing length; support and cell size are 2h */
+    double h;                /* smoothing length; support 2h, cell size 2h + skin */
     double rho0;             /* reference density */
     double alpha;            /* artificial viscosity coefficient */
     double eps;              /* viscosity regulariser (times h^2) */
@@ -118,7 +119,8 @@ typedef struct {
     int32_t use_graph;       /* sph_step_batched replays captured HIP graphs */
     int32_t list_cap;        /* neighbour list per target built by the density
                                 sweep and walked by both sweeps: 0 = default
-                                (96 in 3D, 40 in 2D entries), > 0 = capacity,
+                                (96 in 3D, 40 in 2D entries, times
+                                ((2h + skin) / 2h)^dim), > 0 = capacity,
                                 -1 = no list (both sweeps traverse the stencil).
                                 A target with more neighbours than the capacity
                                 traverses the stencil instead (same results)
@@ -136,7 +138,12 @@ typedef struct {
     double cfl_adv;          /* SPH_SCHEME_DUAL: advection Courant number (0.25) */
     double eta;              /* SPH_SCHEME_DUAL: slope of the Riemann dissipation
                                 limiter (3) */
-    int32_t reserved[4];
+    double skin;             /* Verlet skin (0 <= skin <= 2h; 0 = none): cells of
+                                2h + skin, lists of the neighbours within
+                                2h + skin, both reused by sph_step_batched
+                                until the particles may have moved skin / 2
+                                (below).  Not with SPH_SCHEME_DUAL */
+    int32_t reserved[2];
 } sph_params;
 
 typedef struct {
@@ -170,7 +177,7 @@ typedef struct {
     size_t workspace_bytes;
     double sigma0;           /* lattice number density (1/m^d) */
     double mass;             /* particle mass rho0/sigma0 */
-    double cell_size;        /* 2h */
+    double cell_size;        /* 2h + skin */
     int64_t steps_done;      /* steps since sph_prime */
     int64_t substeps_done;   /* SPH_SCHEME_DUAL: acoustic sub-steps since
                                 sph_prime (per step, the largest count over
@@ -183,8 +190,8 @@ typedef struct sph_ctx sph_ctx;
 const char *sph_last_error(void);
 
 /* Validate and copy the parameters; derive sigma0, the particle mass, the cell
- * grid of every instance (origin tank_lo - 3 dx, ceil((tank extent + 6 dx)/2h)
- * cells per axis, x fastest) and the workspace layout.  No device memory is
+ * grid of every instance (origin tank_lo - 3 dx, ceil((tank extent + 6 dx) /
+ * (2h + skin)) cells per axis, x fastest) and the workspace layout.  No device memory is
  * touched.  On success *out owns a context to be released by sph_destroy. */
 sph_status sph_create(const sph_params *p, sph_ctx **out);
 
@@ -264,9 +271,28 @@ sph_status sph_integrate(sph_ctx *ctx, int32_t half, void *stream);
  * SPH_SCHEME_WCSPH only and return SPH_E_UNSUPPORTED otherwise. */
 sph_status sph_step_batched(sph_ctx *ctx, int32_t n_steps, void *stream);
 
+/* Verlet skin (skin > 0; an extension of the cell linked list and direct
+ * search of the paper's Sec. 5, after Verlet 1967): a build sorts the
+ * particles into cells of 2h + skin and lists, per particle, the neighbours
+ * closer than 2h + skin; every step walks those lists, skipping entries at 2h
+ * or beyond, so each step sees exactly the pairs closer than 2h, as without a
+ * skin (sums in list order).  The reductions that end a step bound the next
+ * drift of every particle by dt (max|v| + dt max|a| / 2) per instance and add
+ * the largest bound to the total since the last build; the next step rebuilds
+ * when twice that total reaches skin (1 - 1e-4), all on the device, so
+ * sph_step_batched stays asynchronous and graph replays stay valid.  Between
+ * builds key[], perm[], cell_start[] and the neighbour list are those of the
+ * last build; count[] is recounted every step.  The stage calls return
+ * SPH_E_UNSUPPORTED when a skin is set. */
+
 /* SPH_SCHEME_DUAL: the acoustic sub-step count of the next advection step of
  * each instance (n[0..B-1]).  Synchronises `stream`. */
 sph_status sph_substeps(sph_ctx *ctx, int32_t *n, void *stream);
+
+/* Number of cell-table builds (each with its neighbour lists) since
+ * sph_prime, the prime's own included: steps_done + 1 without a skin.
+ * Synchronises `stream` when a skin is set. */
+sph_status sph_cell_builds(sph_ctx *ctx, int64_t *n, void *stream);
 
 /* Synchronise `stream`, return the sticky device flags and clear them. */
 sph_status sph_poll_errors(sph_ctx *ctx, uint32_t *flags, void *stream);

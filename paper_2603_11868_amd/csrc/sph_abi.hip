@@ -96,11 +96,12 @@ struct sph_ctx {
     bool list_valid = false;  // the neighbour list matches the current sorted order
     bool mixed = false;
     bool dual = false;        // dual-criteria Riemann scheme
+    bool skin = false;        // Verlet skin: the device decides when to rebuild
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
         o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
-        o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax;
+        o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax, o_gate, o_disp;
     // state
     bool bound = false, primed = false, cells_built = false;
     sph_buffers buf{};
@@ -219,6 +220,9 @@ void build_layout(sph_ctx *c)
     c->o_nsub = take(sizeof(int) * c->idev.size());
     c->o_dtsub = take(sizeof(double) * c->idev.size());
     c->o_nsubmax = take(sizeof(int));
+    // Verlet skin: rebuild / reorder gates, counters and displacement bounds
+    c->o_gate = take(sizeof(int) * 8);
+    c->o_disp = take(sizeof(double) * 2);
     c->ws_bytes = off;
 }
 
@@ -291,12 +295,13 @@ sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
     c->list_valid = false;
     {
         StageTimer t(c, ST_SCAN, s, timed);
-        TRY(check_launch(launch_exclusive_scan(d.cnt, d.cell_start, c->C + 1, d.part, 1, s), "cell scan"));
+        TRY(check_launch(launch_exclusive_scan(d.cnt, d.cell_start, c->C + 1, d.part, 1, s, d.gate),
+                         "cell scan"));
     }
     {
         StageTimer t(c, ST_SORT, s, timed);
         TRY(check_launch(launch_radix_sort(d.key, c->N, c->C, d.skey, d.perm, d.rk0, d.rv0, d.rk1,
-                                           d.rv1, d.hist, d.part, s),
+                                           d.rv1, d.hist, d.part, s, d.gate),
                          "radix sort"));
     }
     if (reorder) {
@@ -329,6 +334,9 @@ sph_status do_reduce(sph_ctx *c, int prime, hipStream_t s, bool timed)
 
 bool reorder_due(const sph_ctx *c)
 {
+    // with a skin the reorder kernels are always enqueued and the device runs
+    // them on a rebuild at least reorder_every steps after the last reorder
+    if (c->skin) return c->p.reorder_every > 0;
     return c->p.reorder_every > 0 && (c->steps_done % c->p.reorder_every) == 0;
 }
 
@@ -460,7 +468,11 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
         return fail(SPH_E_ARG, "alpha >= 0, eps > 0 and positive Courant numbers required");
     const int block = p->block_threads == 0 ? 256 : p->block_threads;
     if (block != 64 && block != 128 && block != 256) return fail(SPH_E_ARG, "block_threads must be 0, 64, 128 or 256");
-    int lcap = p->list_cap == 0 ? (p->dim == 3 ? 96 : 40) : (p->list_cap < 0 ? 0 : p->list_cap);
+    if (!(p->skin >= 0.0 && p->skin <= 2.0 * p->h)) return fail(SPH_E_ARG, "skin must be in [0, 2h]");
+    // default capacity: the neighbours within 2h + skin, scaled from 2h
+    const double grow = std::pow((2.0 * p->h + p->skin) / (2.0 * p->h), p->dim);
+    int lcap = p->list_cap == 0 ? (int)std::ceil((p->dim == 3 ? 96 : 40) * grow)
+                                : (p->list_cap < 0 ? 0 : p->list_cap);
     lcap = (lcap + 3) & ~3;   // stored in quads
     const int pref = p->prefetch == 0 ? 8 : p->prefetch;
     if (pref != 4 && pref != 8) return fail(SPH_E_ARG, "prefetch must be 0, 4 or 8");
@@ -471,6 +483,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
         if (p->use_graph) return fail(SPH_E_UNSUPPORTED, "the dual scheme does not replay graphs");
         if (!(p->cfl_adv > 0.0) || !(p->eta >= 0.0))
             return fail(SPH_E_ARG, "the dual scheme needs cfl_adv > 0 and eta >= 0");
+        if (p->skin > 0.0) return fail(SPH_E_UNSUPPORTED, "the dual scheme rebuilds its cells every advection step");
     }
     auto *c = new sph_ctx();
     c->p = *p;
@@ -480,8 +493,9 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     c->pref = pref;
     c->mixed = p->precision == SPH_MIXED;
     c->dual = p->scheme == SPH_SCHEME_DUAL;
+    c->skin = p->skin > 0.0;
     c->inst.assign(p->inst, p->inst + p->n_instances);
-    const double cs = 2.0 * p->h;
+    const double cs = 2.0 * p->h + p->skin;
     int64_t N = 0, Nw = 0, C = 0;
     c->idev.resize(c->inst.size());
     for (size_t b = 0; b < c->inst.size(); ++b) {
@@ -519,7 +533,10 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     sc.inv_h = 1.0 / p->h;
     sc.cs = cs;
     sc.inv_cs = 1.0 / cs;
-    sc.cut2 = cs * cs;
+    sc.cut2 = (2.0 * p->h) * (2.0 * p->h);
+    sc.bcut2 = cs * cs;
+    sc.skin = p->skin;
+    sc.reorder_every = p->reorder_every;
     sc.rho0 = p->rho0;
     sc.sigma0 = lattice_number_density(p->dim, p->dx, p->h);
     sc.mass = p->rho0 / sc.sigma0;
@@ -540,6 +557,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     sc.finv_h = (float)sc.inv_h;
     sc.fcs = (float)cs;
     sc.fcut2 = (float)sc.cut2;
+    sc.fbcut2 = (float)sc.bcut2;
     sc.fkW = (float)sc.kW;
     sc.fkF = (float)sc.kF;
     sc.feps_h2 = (float)sc.eps_h2;
@@ -648,6 +666,8 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.nsub = reinterpret_cast<int *>(ws + c->o_nsub);
     d.dtsub = reinterpret_cast<double *>(ws + c->o_dtsub);
     d.nsub_max = reinterpret_cast<int *>(ws + c->o_nsubmax);
+    d.gate = c->skin ? reinterpret_cast<int *>(ws + c->o_gate) : nullptr;
+    d.disp = c->skin ? reinterpret_cast<double *>(ws + c->o_disp) : nullptr;
     if (!c->fmap.empty())
         HIP_TRY(hipMemcpyAsync(d.fmap, c->fmap.data(), sizeof(Chunk) * c->fmap.size(), hipMemcpyHostToDevice, s));
     if (!c->wmap.empty())
@@ -684,6 +704,16 @@ sph_status sph_prime(sph_ctx *c, void *stream)
     if (c->dual) {
         TRY(dual_prime(c, s));
     } else {
+        if (c->skin) {
+            // the prime builds; its reduction plans the first step.  The
+            // first rebuild after it reorders (as the first step does
+            // without a skin).
+            const int K = c->p.reorder_every;
+            HIP_TRY(launch_fill_i32(d.gate, 8, 0, s));
+            HIP_TRY(launch_fill_i32(d.gate, 1, 1, s));
+            HIP_TRY(launch_fill_i32(d.gate + 2, 1, K > 0 ? K - 1 : 0, s));
+            HIP_TRY(launch_fill_f64(d.disp, 2, 0.0, s));
+        }
         TRY(do_keys(c, 0, s, false));
         TRY(do_sort(c, false, s, false));
         TRY(do_density(c, 0, s, false));
@@ -703,6 +733,7 @@ sph_status sph_build_cells(sph_ctx *c, void *stream)
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
+    if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     if (c->cells_built) return fail(SPH_E_STATE, "cells already built: call sph_sort first");
     TRY(do_keys(c, 0, as_stream(stream), c->timing));
     c->cells_built = true;
@@ -714,6 +745,7 @@ sph_status sph_sort(sph_ctx *c, int32_t reorder, void *stream)
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
+    if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     if (!c->cells_built) return fail(SPH_E_STATE, "sph_build_cells (or sph_integrate half 1) first");
     TRY(do_sort(c, reorder != 0, as_stream(stream), c->timing));
     c->cells_built = false;
@@ -725,6 +757,7 @@ sph_status sph_density(sph_ctx *c, void *stream)
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
+    if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     return do_density(c, 1, as_stream(stream), c->timing);
 }
 
@@ -733,6 +766,7 @@ sph_status sph_forces(sph_ctx *c, void *stream)
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
+    if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     return do_force(c, 0, as_stream(stream), c->timing);
 }
 
@@ -741,6 +775,7 @@ sph_status sph_integrate(sph_ctx *c, int32_t half, void *stream)
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
+    if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     if (half != 1 && half != 2) return fail(SPH_E_ARG, "half must be 1 or 2");
     hipStream_t s = as_stream(stream);
     if (half == 1) {
@@ -791,6 +826,22 @@ sph_status sph_substeps(sph_ctx *c, int32_t *n, void *stream)
     hipStream_t s = as_stream(stream);
     HIP_TRY(hipMemcpyAsync(n, c->dev.nsub, sizeof(int32_t) * c->idev.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return SPH_OK;
+}
+
+sph_status sph_cell_builds(sph_ctx *c, int64_t *n, void *stream)
+{
+    if (!c || !n) return fail(SPH_E_ARG, "null argument");
+    if (!c->bound || !c->primed) return fail(SPH_E_STATE, "sph_bind and sph_prime first");
+    if (!c->skin) {
+        *n = c->steps_done + 1;
+        return SPH_OK;
+    }
+    hipStream_t s = as_stream(stream);
+    int32_t host[8] = {0};
+    HIP_TRY(hipMemcpyAsync(host, c->dev.gate, sizeof(host), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n = host[4];
     return SPH_OK;
 }
 

@@ -53,12 +53,16 @@ struct InstDev {
 struct SimConst {
     int dim, n_inst, N, Nw, C;
     int scheme;                        // 0 WCSPH step, 1 dual-criteria Riemann scheme
-    double h, inv_h, cs, inv_cs, cut2;
+    double h, inv_h, cs, inv_cs, cut2;  // cell size 2h + skin; cut2 = (2h)^2, the pair cutoff
     double rho0, mass, sigma0, alpha, eps_h2, cfl_ac, cfl_f;
     double kW, kF, W0;                 // W = kW t^4 (2q+1), F = kF t^3, t = 1 - q/2
     double g[3];
     double cfl_adv, cfl_sub, eta;      // dual scheme: advection and acoustic Courant numbers, limiter
-    float fh, finv_h, fcs, fcut2, fkW, fkF, feps_h2, pad1;
+    double bcut2;                      // (2h + skin)^2: radius of the cell stencil and the list build
+    double skin;                       // Verlet skin (0: cells and lists rebuilt every step)
+    int reorder_every;                 // with a skin: reorder at a rebuild this many steps after the last
+    int pad0;
+    float fh, finv_h, fcs, fcut2, fkW, fkF, feps_h2, fbcut2;
     float fg[3], pad2;
 };
 

@@ -91,11 +91,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_keys(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     double *__restrict__ x, double *__restrict__ v, const double *__restrict__ a,
     const double *__restrict__ dt, int kick_on, int n, int *__restrict__ key,
-    int *__restrict__ cnt, int *__restrict__ clampc, unsigned *__restrict__ flags)
+    int *__restrict__ cnt, int *__restrict__ clampc, unsigned *__restrict__ flags,
+    const int *__restrict__ gate)
 {
     const Chunk ch = map[blockIdx.x];
     const int i = ch.begin + threadIdx.x;
     const bool act = i < ch.end;
+    // a step that reuses its cell table only kicks and drifts
+    const bool build = gate == nullptr || *gate != 0;
     int k = 0;
     int clamped = 0;
     if (act) {
@@ -113,12 +116,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_keys(
                 x[(int64_t)c * n + i] = xi[c];
             }
         }
-        int cc[3] = {0, 0, 0};
+        if (build) {
+            int cc[3] = {0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) cc[c] = cell_1d(xi[c], I.lo[c], sc.inv_cs, I.ncell[c], clamped);
-        k = I.cell_base + cc[0] + I.ncell[0] * (cc[1] + I.ncell[1] * cc[2]);
-        key[i] = k;
+            for (int c = 0; c < DIM; ++c) cc[c] = cell_1d(xi[c], I.lo[c], sc.inv_cs, I.ncell[c], clamped);
+            k = I.cell_base + cc[0] + I.ncell[0] * (cc[1] + I.ncell[1] * cc[2]);
+            key[i] = k;
+        }
     }
+    if (!build) return;
     aggregated_count(cnt, k, act);
     const uint64_t cm = __ballot(act && clamped);
     if (cm && lane_id() == 0) {
@@ -132,10 +138,10 @@ hipError_t launch_keys(const SimConst &sc, const Dev &d, int kick_on, hipStream_
     if (d.nfchunks <= 0) return hipSuccess;
     if (sc.dim == 2)
         k_keys<2><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.inst, d.x, d.v, d.a, d.dt, kick_on,
-                                                  sc.N, d.key, d.cnt, d.clampc, d.flags);
+                                                  sc.N, d.key, d.cnt, d.clampc, d.flags, d.gate);
     else
         k_keys<3><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.inst, d.x, d.v, d.a, d.dt, kick_on,
-                                                  sc.N, d.key, d.cnt, d.clampc, d.flags);
+                                                  sc.N, d.key, d.cnt, d.clampc, d.flags, d.gate);
     return hipGetLastError();
 }
 
@@ -146,10 +152,10 @@ hipError_t launch_wall_keys(const SimConst &sc, const Dev &d, hipStream_t s)
     double *xw = const_cast<double *>(d.xw);
     if (sc.dim == 2)
         k_keys<2><<<d.nwchunks, d.block, 0, s>>>(sc, d.wmap, d.inst, xw, nullptr, nullptr, d.dt, 0,
-                                                  sc.Nw, d.wkey, d.cnt, d.clampc, d.flags);
+                                                  sc.Nw, d.wkey, d.cnt, d.clampc, d.flags, nullptr);
     else
         k_keys<3><<<d.nwchunks, d.block, 0, s>>>(sc, d.wmap, d.inst, xw, nullptr, nullptr, d.dt, 0,
-                                                  sc.Nw, d.wkey, d.cnt, d.clampc, d.flags);
+                                                  sc.Nw, d.wkey, d.cnt, d.clampc, d.flags, nullptr);
     return hipGetLastError();
 }
 
@@ -161,8 +167,9 @@ template <int DIM>
 __global__ __launch_bounds__(kMaxBlock) void k_reorder_gather(
     const Chunk *__restrict__ map, const int *__restrict__ perm, const double *__restrict__ x,
     const double *__restrict__ v, const double *__restrict__ rho, const int *__restrict__ id,
-    double *__restrict__ scr, int n)
+    double *__restrict__ scr, int n, const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     if (k >= ch.end) return;
@@ -180,8 +187,9 @@ template <int DIM>
 __global__ __launch_bounds__(kMaxBlock) void k_reorder_copy(
     const Chunk *__restrict__ map, const double *__restrict__ scr, const int *__restrict__ skey,
     double *__restrict__ x, double *__restrict__ v, double *__restrict__ rho,
-    int *__restrict__ id, int *__restrict__ perm, int *__restrict__ key, int n)
+    int *__restrict__ id, int *__restrict__ perm, int *__restrict__ key, int n, const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     if (k >= ch.end) return;
@@ -199,12 +207,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_reorder_copy(
 hipError_t launch_reorder(const SimConst &sc, const Dev &d, hipStream_t s)
 {
     if (d.nfchunks <= 0) return hipSuccess;
+    // with a skin the reduction of the previous step decides (gate[1])
+    const int *g = d.gate ? d.gate + 1 : nullptr;
     if (sc.dim == 2) {
-        k_reorder_gather<2><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.perm, d.x, d.v, d.rho, d.id, d.scratch, sc.N);
-        k_reorder_copy<2><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.scratch, d.skey, d.x, d.v, d.rho, d.id, d.perm, d.key, sc.N);
+        k_reorder_gather<2><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.perm, d.x, d.v, d.rho, d.id, d.scratch, sc.N, g);
+        k_reorder_copy<2><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.scratch, d.skey, d.x, d.v, d.rho, d.id, d.perm, d.key, sc.N, g);
     } else {
-        k_reorder_gather<3><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.perm, d.x, d.v, d.rho, d.id, d.scratch, sc.N);
-        k_reorder_copy<3><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.scratch, d.skey, d.x, d.v, d.rho, d.id, d.perm, d.key, sc.N);
+        k_reorder_gather<3><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.perm, d.x, d.v, d.rho, d.id, d.scratch, sc.N, g);
+        k_reorder_copy<3><<<d.nfchunks, d.block, 0, s>>>(d.fmap, d.scratch, d.skey, d.x, d.v, d.rho, d.id, d.perm, d.key, sc.N, g);
     }
     return hipGetLastError();
 }
@@ -263,11 +273,43 @@ hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kic
 
 constexpr int kReduceBlock = 1024;     // one block per instance: wide, to keep many rows in flight
 
+// Verlet skin: called once per instance (thread 0 of its reduction block)
+// with the step dt_n it planned and the max|v|, max|a| the next drift starts
+// from.  That drift moves a particle by dt_n (|v| + dt_n |a| / 2) at most.
+// The last instance to arrive plans the next step: while twice the summed
+// bounds since the last build stay below the skin, every pair closer than 2h
+// was closer than 2h + skin at the build, so the cell table and the lists of
+// that build still hold all of them; otherwise the next step rebuilds both.
+__device__ void skin_plan(const SimConst &sc, int *__restrict__ gate, double *__restrict__ disp,
+                          double dt_n, double vmax, double amax)
+{
+    double bound = dt_n * (vmax + 0.5 * dt_n * amax);
+    if (!(bound >= 0.0 && bound < 1e300)) bound = 1e300;     // non-finite state: rebuild
+    auto *bits = reinterpret_cast<unsigned long long *>(disp + 1);
+    atomicMax(bits, (unsigned long long)__double_as_longlong(bound));
+    __threadfence();
+    if (atomicAdd(&gate[3], 1) != sc.n_inst - 1) return;
+    __threadfence();
+    const double next = __longlong_as_double((long long)atomicExch(bits, 0ull));
+    const bool built = gate[0] != 0;
+    const bool reordered = gate[1] != 0;
+    const double since_build = (built ? 0.0 : disp[0]) + next;
+    // margin: far above the rounding of positions and of FP32 pair distances
+    const bool rebuild = !(2.0 * since_build < sc.skin * (1.0 - 1e-4));
+    disp[0] = rebuild ? 0.0 : since_build;
+    int since = reordered ? 1 : gate[2] + (gate[2] < (1 << 30) ? 1 : 0);
+    gate[0] = rebuild ? 1 : 0;
+    gate[1] = (rebuild && sc.reorder_every > 0 && since >= sc.reorder_every) ? 1 : 0;
+    gate[2] = since;
+    gate[3] = 0;
+    if (built) gate[4] += 1;
+}
+
 __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
     SimConst sc, const InstDev *__restrict__ inst, const double *__restrict__ partials,
     double *__restrict__ dt, double *__restrict__ diag, int *__restrict__ clampc,
     unsigned *__restrict__ flags, int prime, int *__restrict__ nsub, double *__restrict__ dtsub,
-    int *__restrict__ nsub_max)
+    int *__restrict__ nsub_max, int *__restrict__ gate, double *__restrict__ disp)
 {
     const int b = blockIdx.x;
     const InstDev &I = inst[b];
@@ -330,6 +372,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
             const double dt_ac = sc.cfl_ac * sc.h / (I.c0 + vmax);
             const double dt_f = sc.cfl_f * sqrt(sc.h / amax);
             dt[b] = dt_ac < dt_f ? dt_ac : dt_f;
+            if (gate) skin_plan(sc, gate, disp, dt[b], vmax, amax);
         }
         if (tot[P_BAD] > 0.0) atomicOr(flags, 2u);
     }
@@ -339,7 +382,7 @@ hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipS
 {
     if (sc.n_inst <= 0) return hipSuccess;
     k_final_reduce<<<sc.n_inst, kReduceBlock, 0, s>>>(sc, d.inst, d.partials, d.dt, d.diag, d.clampc, d.flags, prime,
-                                                      d.nsub, d.dtsub, d.nsub_max);
+                                                      d.nsub, d.dtsub, d.nsub_max, d.gate, d.disp);
     return hipGetLastError();
 }
 

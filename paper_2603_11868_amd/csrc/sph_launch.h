@@ -10,11 +10,13 @@ int scan_tiles(int64_t n);
 int64_t scan_max_elems();
 int radix_tiles(int64_t n);
 int radix_passes(int64_t ncells);
+// gate: null, or a device int; every kernel of the call returns at once
+// when *gate == 0 (a step that reuses its cell table).
 hipError_t launch_exclusive_scan(int *in, int *out, int64_t n, int *part, int zero_in,
-                                 hipStream_t s);
+                                 hipStream_t s, const int *gate = nullptr);
 hipError_t launch_radix_sort(const int *keys, int64_t n, int64_t ncells, int *skey, int *perm,
                              int *k0, int *v0, int *k1, int *v1, int *hist, int *part,
-                             hipStream_t s);
+                             hipStream_t s, const int *gate = nullptr);
 
 // ---- physics (sph_kernels.hip, sph_sweeps.hip) ----------------------------
 struct Dev {
@@ -48,6 +50,13 @@ struct Dev {
     int *nsub;                // [B] acoustic sub-steps of the next advection step
     double *dtsub;            // [B] their size
     int *nsub_max;            // [1] max over instances
+    // Verlet skin (null / unused without one): gate[0] rebuild the cell table
+    // and the list this step, gate[1] reorder this step, gate[2] steps since
+    // the last reorder, gate[3] reduction blocks done, gate[4] builds since
+    // the prime; disp[0] displacement bound since the last build, disp[1] the
+    // largest bound of the next drift over the instances (as ordered bits)
+    int *gate;
+    double *disp;
 };
 
 hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s);

@@ -29,8 +29,9 @@ int64_t scan_max_elems() { return (int64_t)SCAN_TOP_BS * SCAN_TOP_IPT * SCAN_TIL
 int radix_tiles(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
 
 __global__ __launch_bounds__(SCAN_BS) void k_scan_reduce(const int *__restrict__ in, int n,
-                                                         int *__restrict__ part)
+                                                         int *__restrict__ part, const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int lds[SCAN_BS / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
     int s = 0;
@@ -44,8 +45,10 @@ __global__ __launch_bounds__(SCAN_BS) void k_scan_reduce(const int *__restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(SCAN_TOP_BS) void k_scan_top(int *__restrict__ part, int ntiles)
+__global__ __launch_bounds__(SCAN_TOP_BS) void k_scan_top(int *__restrict__ part, int ntiles,
+                                                           const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int lds[SCAN_TOP_BS / 64 + 1];
     const int base = threadIdx.x * SCAN_TOP_IPT;
     int v[SCAN_TOP_IPT];
@@ -68,8 +71,9 @@ __global__ __launch_bounds__(SCAN_TOP_BS) void k_scan_top(int *__restrict__ part
 
 __global__ __launch_bounds__(SCAN_BS) void k_scan_apply(int *__restrict__ in, int *__restrict__ out,
                                                         int n, const int *__restrict__ part,
-                                                        int zero_in)
+                                                        int zero_in, const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int lds[SCAN_BS / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
     int v[SCAN_IPT];
@@ -95,14 +99,14 @@ __global__ __launch_bounds__(SCAN_BS) void k_scan_apply(int *__restrict__ in, in
 
 // Exclusive scan of n ints (out may alias in).  part: scan_tiles(n) ints.
 hipError_t launch_exclusive_scan(int *in, int *out, int64_t n, int *part, int zero_in,
-                                 hipStream_t s)
+                                 hipStream_t s, const int *gate)
 {
     if (n <= 0) return hipSuccess;
     if (n > scan_max_elems()) return hipErrorInvalidValue;
     int nt = scan_tiles(n);
-    k_scan_reduce<<<nt, SCAN_BS, 0, s>>>(in, (int)n, part);
-    k_scan_top<<<1, SCAN_TOP_BS, 0, s>>>(part, nt);
-    k_scan_apply<<<nt, SCAN_BS, 0, s>>>(in, out, (int)n, part, zero_in);
+    k_scan_reduce<<<nt, SCAN_BS, 0, s>>>(in, (int)n, part, gate);
+    k_scan_top<<<1, SCAN_TOP_BS, 0, s>>>(part, nt, gate);
+    k_scan_apply<<<nt, SCAN_BS, 0, s>>>(in, out, (int)n, part, zero_in, gate);
     return hipGetLastError();
 }
 
@@ -121,8 +125,9 @@ __device__ __forceinline__ uint64_t match_digit(unsigned d, bool valid)
 
 __global__ __launch_bounds__(RS_BS) void k_radix_hist(const int *__restrict__ keys, int n,
                                                       int shift, int *__restrict__ hist,
-                                                      int ntiles)
+                                                      int ntiles, const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int h[RS_RADIX];
     const int tid = threadIdx.x;
     h[tid] = 0;
@@ -144,8 +149,10 @@ __global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__
                                                          int shift,
                                                          const int *__restrict__ hist, int ntiles,
                                                          int *__restrict__ kout,
-                                                         int *__restrict__ vout)
+                                                         int *__restrict__ vout,
+                                                         const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int base[RS_RADIX];
     __shared__ int wc[RS_BS / 64][RS_RADIX];
     const int tid = threadIdx.x;
@@ -198,7 +205,7 @@ int radix_passes(int64_t ncells)
 // (n ints each), hist (RS_RADIX * radix_tiles(n)), part (scan tiles).
 hipError_t launch_radix_sort(const int *keys, int64_t n, int64_t ncells, int *skey, int *perm,
                              int *k0, int *v0, int *k1, int *v1, int *hist, int *part,
-                             hipStream_t s)
+                             hipStream_t s, const int *gate)
 {
     if (n <= 0) return hipSuccess;
     const int nt = radix_tiles(n);
@@ -211,10 +218,10 @@ hipError_t launch_radix_sort(const int *keys, int64_t n, int64_t ncells, int *sk
         if (p == passes - 1) { ko = skey; vo = perm; }
         else if (p % 2 == 0) { ko = k0; vo = v0; }
         else { ko = k1; vo = v1; }
-        k_radix_hist<<<nt, RS_BS, 0, s>>>(kin, (int)n, shift, hist, nt);
-        hipError_t e = launch_exclusive_scan(hist, hist, (int64_t)RS_RADIX * nt, part, 0, s);
+        k_radix_hist<<<nt, RS_BS, 0, s>>>(kin, (int)n, shift, hist, nt, gate);
+        hipError_t e = launch_exclusive_scan(hist, hist, (int64_t)RS_RADIX * nt, part, 0, s, gate);
         if (e != hipSuccess) return e;
-        k_radix_scatter<<<nt, RS_BS, 0, s>>>(kin, vin, (int)n, shift, hist, nt, ko, vo);
+        k_radix_scatter<<<nt, RS_BS, 0, s>>>(kin, vin, (int)n, shift, hist, nt, ko, vo, gate);
         kin = ko;
         vin = vo;
     }

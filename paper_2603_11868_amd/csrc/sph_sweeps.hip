@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     const double *__restrict__ x, const double *__restrict__ v, const int *__restrict__ perm,
     const int *__restrict__ skey, int n, typename Rec<DIM, MIXED>::v4 *__restrict__ rec,
-    typename Cand<DIM>::t *__restrict__ cpos)
+    typename Cand<DIM>::t *__restrict__ cpos, const int *__restrict__ gate)
 {
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
@@ -242,7 +242,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack(
         A.x = p[0]; A.y = p[1]; A.z = (real)vi[0]; A.w = (real)vi[1];
     }
     rec[2 * (int64_t)k] = A;
-    if constexpr (!MIXED) {
+    // the FP32 copies serve the candidate tests, which only a build runs
+    if (!MIXED && (gate == nullptr || *gate != 0)) {
         typename Cand<DIM>::t cp;
         cp.x = o[0];
         cp.y = o[1];
@@ -291,7 +292,7 @@ static void pack_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
 {
     k_pack<DIM, MIXED><<<d.nfchunks, d.block, 0, s>>>(
         sc, d.fmap, d.inst, d.x, d.v, d.perm, d.skey, sc.N,
-        static_cast<typename Rec<DIM, MIXED>::v4 *>(d.rec), static_cast<typename Cand<DIM>::t *>(d.cpos));
+        static_cast<typename Rec<DIM, MIXED>::v4 *>(d.rec), static_cast<typename Cand<DIM>::t *>(d.cpos), d.gate);
 }
 
 hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
@@ -354,10 +355,12 @@ __device__ __forceinline__ void target_offsets(const SimConst &sc, const InstDev
 }
 
 // Stencil row (dy, dz) of a target with in-cell offsets o: false when every
-// point of the row is at least 2h away, else the x range of cells that can
-// hold a neighbour.  cut2m is (2h)^2 enlarged by a margin far above the
-// rounding of o, so a skipped cell never holds a particle that passes the
-// r^2 < (2h)^2 predicate: the neighbour set is unchanged.
+// point of the row is at least 2h + skin away, else the x range of cells that
+// can hold a neighbour.  cut2m is (2h + skin)^2 enlarged by a margin far above
+// the rounding of o, so a skipped cell never holds a particle that passes the
+// r^2 < (2h + skin)^2 predicate.  With a skin the cells are those of the last
+// build and particles have moved by less than skin / 2 since, so a particle
+// closer than 2h is never skipped either.
 template <class real>
 __device__ __forceinline__ bool row_cells(const real *o, real cs, real cut2m, int dy, int dz, int cx,
                                           int ncx, int &xlo, int &xhi)
@@ -377,8 +380,8 @@ __device__ __forceinline__ bool row_cells(const real *o, real cs, real cut2m, in
 template <bool MIXED>
 __device__ __forceinline__ auto cull_margin(const SimConst &sc)
 {
-    if constexpr (MIXED) return sc.fcut2 * (float)(1.0 + 1e-5);
-    else return sc.cut2 * (1.0 + 1e-9);
+    if constexpr (MIXED) return sc.fbcut2 * (float)(1.0 + 1e-5);
+    else return sc.bcut2 * (1.0 + 1e-9);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +488,7 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
     const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
     const real cut2m = cull_margin<MIXED>(sc);
-    const float fcs = sc.fcs, fcut2 = sc.fcut2;
+    const float fcs = sc.fcs, fcut2 = sc.fbcut2;       // the build radius (2h + skin)
     real o[3];
     target_offsets<DIM, MIXED>(sc, I, c, pi, o);
     float lo = fcut2 * (1.0f - 1e-4f), hi = fcut2 * (1.0f + 1e-4f);
@@ -557,7 +560,7 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
                                 if (pass == 0) V::pos(V::loadA(rec, s), pj);
                                 else V::wall_pos(wpos[s], pj);
                                 sub_vec<DIM>(pi, pj, rr);
-                                hit = norm2<DIM>(rr) < (real)sc.cut2;
+                                hit = norm2<DIM>(rr) < (real)sc.bcut2;
                             }
                         }
                         if (hit) {
@@ -590,7 +593,8 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
 
 // Phase 2: fn(wall, s, r, r2, A_j, B_j) for the first m (<= cap) entries of
 // target k; the records of U entries are fetched before any of them is used.
-template <int DIM, bool MIXED, int U, int NEED, class Fn>
+// CHK: the list was built with a skin, so entries at 2h or beyond are skipped.
+template <int DIM, bool MIXED, int U, int NEED, bool CHK = false, class Fn>
 __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
                                           const typename RV<DIM, MIXED>::real *pi,
                                           const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
@@ -642,7 +646,9 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
                         shift_target<DIM, false>(pi, 0, 0, 0, cs, t);
                     }
                     sub_vec<DIM>(t, pj, r);
-                    fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, norm2<DIM>(r), A[u], B[u]);
+                    const real r2 = norm2<DIM>(r);
+                    if (!CHK || r2 < (MIXED ? (real)sc.fcut2 : (real)sc.cut2))
+                        fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, r2, A[u], B[u]);
                 }
             }
         }
@@ -653,7 +659,10 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
 // density sweep
 // ---------------------------------------------------------------------------
 
-// LIST = 0: direct search.  LIST = 1: build the list, then walk it.
+// LIST = 0: direct search.  LIST = 1: build the list, then walk it.  LIST = 2
+// (Verlet skin): build the list with radius 2h + skin when the previous
+// step's reduction asked for a rebuild (*gate != 0), else walk the list of the
+// last build; entries at 2h or beyond are skipped.
 template <int DIM, bool MIXED, int LIST, int PF>
 __global__ __launch_bounds__(kMaxBlock) void k_density(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
@@ -662,7 +671,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos, const typename Cand<DIM>::t *__restrict__ cpos,
     const typename Cand<DIM>::t *__restrict__ wcpos, double *__restrict__ rho, int *__restrict__ count,
     const double *__restrict__ dt, int use_dt, uint4 *__restrict__ nlist, int *__restrict__ lcount, int cap,
-    unsigned *__restrict__ flags)
+    unsigned *__restrict__ flags, const int *__restrict__ gate)
 {
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
@@ -708,15 +717,21 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
             if constexpr (DIM == 3) ci[2] = cp.z;
             else ci[2] = 0.0f;
         }
-        const int m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
-                                                 nlist, cap, n);
-        if (m <= cap) {
-            walk_list<DIM, MIXED, 4, NEED>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+        const bool build = LIST == 1 || *gate != 0;
+        int m;
+        if (build) {
+            m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+                                           nlist, cap, n);
+            lcount[k] = m;
         } else {
-            atomicOr(flags, 4u);
+            m = lcount[k];
+        }
+        if (m <= cap) {
+            walk_list<DIM, MIXED, 4, NEED, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+        } else {
+            if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         }
-        lcount[k] = m;
     } else {
         for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
     }
@@ -746,14 +761,17 @@ static void density_dispatch(const SimConst &sc, const Dev &d, int use_dt, hipSt
         sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, static_cast<typename R::v4 *>(d.rec),
         static_cast<const typename R::wpos_t *>(d.wpos), static_cast<const typename Cand<DIM>::t *>(d.cpos),
         static_cast<const typename Cand<DIM>::t *>(d.wcpos), d.rho, d.count, d.dt, use_dt, d.nlist, d.lcount,
-        d.list_cap, d.flags);
+        d.list_cap, d.flags, d.gate);
 }
 
 template <int DIM, bool MIXED>
 static void density_variant(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
 {
     if (d.list_cap <= 0) density_dispatch<DIM, MIXED, 0, 4>(sc, d, use_dt, s);
-    else if (d.prefetch == 4) density_dispatch<DIM, MIXED, 1, 4>(sc, d, use_dt, s);
+    else if (d.gate) {
+        if (d.prefetch == 4) density_dispatch<DIM, MIXED, 2, 4>(sc, d, use_dt, s);
+        else density_dispatch<DIM, MIXED, 2, 8>(sc, d, use_dt, s);
+    } else if (d.prefetch == 4) density_dispatch<DIM, MIXED, 1, 4>(sc, d, use_dt, s);
     else density_dispatch<DIM, MIXED, 1, 8>(sc, d, use_dt, s);
 }
 
@@ -769,7 +787,8 @@ hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_d
 // force sweep (+ half 2 and all partials when fused)
 // ---------------------------------------------------------------------------
 
-// LIST = 0: direct search.  LIST = 1: walk the list of this step's density sweep.
+// LIST = 0: direct search.  LIST = 1: walk the list of this step's density
+// sweep.  LIST = 2: the same with a Verlet skin (entries at 2h or beyond skipped).
 template <int DIM, bool MIXED, bool FUSED, int LIST>
 __global__ __launch_bounds__(kMaxBlock) void k_force(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
@@ -841,7 +860,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
-            if (m <= cap) walk_list<DIM, MIXED, U, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+            if (m <= cap) walk_list<DIM, MIXED, U, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
             else for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         } else {
             for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -890,7 +909,10 @@ static void force_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
 template <int DIM, bool MIXED>
 static void force_variant(const SimConst &sc, const Dev &d, int fused, int list, hipStream_t s)
 {
-    if (fused) { if (list) force_dispatch<DIM, MIXED, true, 1>(sc, d, s); else force_dispatch<DIM, MIXED, true, 0>(sc, d, s); }
+    if (list && d.gate) {
+        if (fused) force_dispatch<DIM, MIXED, true, 2>(sc, d, s);
+        else force_dispatch<DIM, MIXED, false, 2>(sc, d, s);
+    } else if (fused) { if (list) force_dispatch<DIM, MIXED, true, 1>(sc, d, s); else force_dispatch<DIM, MIXED, true, 0>(sc, d, s); }
     else { if (list) force_dispatch<DIM, MIXED, false, 1>(sc, d, s); else force_dispatch<DIM, MIXED, false, 0>(sc, d, s); }
 }
 

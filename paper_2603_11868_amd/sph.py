@@ -36,7 +36,7 @@ SYMBOLS = ("sph_last_error", "sph_create", "sph_destroy", "sph_get_info", "sph_g
            "sph_workspace_size", "sph_bind", "sph_prime", "sph_build_cells", "sph_sort",
            "sph_density", "sph_forces", "sph_integrate", "sph_step_batched",
            "sph_poll_errors", "sph_set_timing", "sph_stage_times", "sph_stage_name",
-           "sph_stage_count", "sph_substeps")
+           "sph_stage_count", "sph_substeps", "sph_cell_builds")
 
 SPH_SCHEME_WCSPH, SPH_SCHEME_DUAL = 0, 1
 # parameters of the dual-criteria scheme as published (advection and acoustic
@@ -63,7 +63,8 @@ class sph_params(C.Structure):
                 ("inst", C.POINTER(sph_instance_desc)), ("block_threads", C.c_int32),
                 ("use_graph", C.c_int32), ("list_cap", C.c_int32),
                 ("prefetch", C.c_int32), ("scheme", C.c_int32), ("reserved0", C.c_int32),
-                ("cfl_adv", C.c_double), ("eta", C.c_double), ("reserved", C.c_int32 * 4)]
+                ("cfl_adv", C.c_double), ("eta", C.c_double), ("skin", C.c_double),
+                ("reserved", C.c_int32 * 2)]
 
 
 class sph_buffers(C.Structure):
@@ -107,6 +108,7 @@ def lib():
         L.sph_integrate.argtypes = [vp, C.c_int32, vp]
         L.sph_step_batched.argtypes = [vp, C.c_int32, vp]
         L.sph_substeps.argtypes = [vp, C.POINTER(C.c_int32), vp]
+        L.sph_cell_builds.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.sph_poll_errors.argtypes = [vp, C.POINTER(C.c_uint32), vp]
         L.sph_set_timing.argtypes = [vp, C.c_int32]
         L.sph_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32,
@@ -210,6 +212,12 @@ def sph_substeps(ctx, n_instances, stream=None):
     return [int(v) for v in out]
 
 
+def sph_cell_builds(ctx, stream=None) -> int:
+    n = C.c_int64()
+    _check(lib().sph_cell_builds(ctx, C.byref(n), _stream(stream)))
+    return int(n.value)
+
+
 def sph_poll_errors(ctx, stream=None) -> int:
     f = C.c_uint32()
     _check(lib().sph_poll_errors(ctx, C.byref(f), _stream(stream)))
@@ -248,7 +256,7 @@ class Simulation:
     def __init__(self, case, precision="fp64", reorder_every=None, block_threads=0,
                  use_graph=False, device="cuda", alpha=None, g=None,
                  cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0,
-                 scheme="wcsph"):
+                 scheme="wcsph", skin=0.0):
         import torch
         self.torch = torch
         self.case = case
@@ -282,6 +290,7 @@ class Simulation:
         p.use_graph = int(bool(use_graph))
         p.list_cap = int(list_cap)
         p.prefetch = int(prefetch)
+        p.skin = float(skin)               # Verlet skin, a length (0: none)
         if scheme == "dual":
             p.scheme = SPH_SCHEME_DUAL
             p.cfl_ac = DUAL_CFL_AC if cfl is None else float(cfl)
@@ -379,6 +388,9 @@ class Simulation:
     @property
     def steps_done(self):
         return int(sph_get_info(self.ctx).steps_done)
+
+    def cell_builds(self):
+        return sph_cell_builds(self.ctx)
 
     def synchronize(self):
         self.torch.cuda.synchronize(self.device)

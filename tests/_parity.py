@@ -80,3 +80,31 @@ def oracles_for(case, **kw):
 
 def make_case(name):
     return dambreak.make_case(name)
+
+
+def _bound(refs):
+    # the largest drift bound of the next step over the instances
+    return max(r.dt[0] * (r.diag[0] + 0.5 * r.dt[0] * r.diag[1]) for r in refs)
+
+
+class BuildPlan:
+    """The documented rebuild rule, applied to the reference's reductions."""
+
+    def __init__(self, skin):
+        self.skin = skin
+        self.total = 0.0
+        self.builds = 0
+        self.built = True          # the prime builds
+        self.close_calls = 0
+
+    def after_step(self, refs):
+        nxt = _bound(refs)
+        if self.built:
+            self.builds += 1
+        since = (0.0 if self.built else self.total) + nxt
+        lim = self.skin * (1.0 - 1e-4)
+        if abs(2.0 * since - lim) <= 1e-9 * lim:
+            self.close_calls += 1
+        rebuild = not (2.0 * since < lim)
+        self.total = 0.0 if rebuild else since
+        self.built = rebuild

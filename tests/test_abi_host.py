@@ -151,3 +151,44 @@ def test_dual_scheme_options_are_checked(sphmod):
         p, descs = _params(sphmod, case, **dict(base, **over))
         with pytest.raises(sphmod.SphError, match=status):
             sphmod.sph_create(p)
+
+
+def test_skin_options_and_grid(sphmod):
+    import math
+    case = dambreak.make_case("c1_2d")
+    skin = 0.25 * case.h
+    p, descs = _params(sphmod, case, skin=skin)
+    ctx = sphmod.sph_create(p)
+    try:
+        info = sphmod.sph_get_info(ctx)
+        cs = 2 * case.h + skin
+        assert info.cell_size == cs
+        inst = case.instances[0]
+        lo, nc, cb = sphmod.sph_get_grid(ctx, 0)
+        for a in range(case.dim):
+            assert lo[a] == inst.tank_lo[a] - 3 * case.dx
+            assert nc[a] == math.ceil((inst.tank_hi[a] - inst.tank_lo[a] + 6 * case.dx) / cs)
+    finally:
+        sphmod.sph_destroy(ctx)
+    for over, status in ((dict(skin=-1e-3), "E_ARG"), (dict(skin=3 * case.h), "E_ARG"),
+                         (dict(skin=float("nan")), "E_ARG"),
+                         (dict(skin=skin, scheme=sphmod.SPH_SCHEME_DUAL, cfl_adv=0.25, eta=3.0),
+                          "UNSUPPORTED")):
+        p, descs = _params(sphmod, case, **over)
+        with pytest.raises(sphmod.SphError, match=status):
+            sphmod.sph_create(p)
+
+
+def test_skin_scales_the_default_list_capacity(sphmod):
+    # the workspace holds the list: its size grows with ((2h + skin) / 2h)^dim
+    case = dambreak.make_case("tiny_3d")
+    sizes = []
+    for skin in (0.0, 0.5 * case.h):
+        p, descs = _params(sphmod, case, skin=skin)
+        ctx = sphmod.sph_create(p)
+        sizes.append(sphmod.sph_workspace_size(ctx))
+        sphmod.sph_destroy(ctx)
+    n = case.n_fluid
+    grown = 4 * ((int(-(-96 * 1.25 ** 3 // 1)) + 3) // 4) - 96
+    # (less the smaller cell arrays of the coarser grid)
+    assert 0.9 * grown * 4 * n <= sizes[1] - sizes[0] <= grown * 4 * n + 4096

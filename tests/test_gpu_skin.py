@@ -1,0 +1,166 @@
+"""Verlet skin: cells of 2h + skin and neighbour lists reused across steps.
+
+A step with a skin must see exactly the pairs closer than 2h, like a step
+without one, so the whole state follows the FP64 CPU reference to the same
+gates as the plain step, and the per-particle neighbour counts match bit for
+bit.  The rebuild schedule is a pure function of the reductions (dt, max|v|,
+max|a| per instance); it is predicted here from the reference's own
+reductions and compared with the device's build count.  Cell keys, the sort
+permutation and the cell tables are those of cells of 2h + skin at the last
+build, so they are not compared with the reference's cells of 2h.
+"""
+import numpy as np
+import pytest
+
+import dambreak
+from _parity import BuildPlan, errors, gpu_instance_view, oracle_view, oracles_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(case, **kw):
+    from paper_2603_11868_amd import sph
+    return sph.Simulation(case, **kw)
+
+
+def _compare(sim, refs, case, n_done, tol):
+    h = sim.host()
+    for b, r in enumerate(refs):
+        g = gpu_instance_view(sim, h, b)
+        rv = oracle_view(r)
+        e = errors(g, rv, case.instances[b].fluid)
+        print(case.name, b, n_done, e)
+        assert max(e["rho"], e["v"], e["x"]) < (1e-5 if n_done == 1 else 1e-3), e
+        assert max(e["rho"], e["v"], e["x_beyond_rounding"], e["dt"]) < tol, e
+        assert np.array_equal(g["count"], rv["count"]), f"{case.name}[{b}] counts after {n_done}"
+        for slot in (0, 1, 2, 12):
+            assert g["diag"][slot] == pytest.approx(rv["diag"][slot], rel=1e-9, abs=1e-300)
+
+
+@pytest.mark.parametrize("name,skin_h,steps", [("c1_2d", 0.3, 100), ("c1_2d", 0.01, 100),
+                                                ("tiny_3d", 0.05, 100), ("small_batch", 0.005, 60)])
+def test_skin_parity_and_build_schedule_fp64(name, skin_h, steps):
+    case = dambreak.make_case(name)
+    sim = _sim(case, skin=skin_h * case.h)
+    assert sim.info.cell_size == pytest.approx(2 * case.h + skin_h * case.h, rel=1e-15)
+    refs = oracles_for(case)
+    sim.prime()
+    plan = BuildPlan(skin_h * case.h)
+    for r in refs:
+        r.prime()
+    plan.after_step(refs)
+    for n in range(steps):
+        sim.step(1)
+        for r in refs:
+            r.step(1)
+        plan.after_step(refs)
+        if n + 1 in (1, steps):
+            _compare(sim, refs, case, n + 1, 1e-9 if n == 0 else 1e-6)
+    builds = sim.cell_builds()
+    print(name, skin_h, "builds", builds, "predicted", plan.builds, "of", steps + 1)
+    assert abs(builds - plan.builds) <= plan.close_calls
+    assert sim.poll_errors() == 0
+    sim.close()
+
+
+def _same_run(case, ha, hb):
+    """Two GPU runs of one case that sum the same pairs in different orders:
+    bit-exact counts; state differences at the level the FP64 parity gates
+    allow after 100 steps (1e-6 of the displacement and of max|v|)."""
+    oa, ob = np.argsort(ha["id"]), np.argsort(hb["id"])
+    assert np.array_equal(ha["count"][oa], hb["count"][ob])
+    x0 = np.concatenate([i.fluid[:, :case.dim] for i in case.instances], 0)
+    disp = np.abs(ha["x"][oa] - x0).max()
+    e = {"x": np.abs(ha["x"][oa] - hb["x"][ob]).max() / disp,
+         "v": np.abs(ha["v"][oa] - hb["v"][ob]).max() / np.abs(ha["v"]).max(),
+         "rho": np.abs(ha["rho"][oa] - hb["rho"][ob]).max() / case.rho0}
+    print(case.name, "skin vs no skin", e)
+    assert max(e.values()) < 1e-6, e
+
+
+def test_skin_mixed_and_graph_match_eager():
+    """Mixed precision with a skin, eager and graph-replayed: the same kernels
+    in the same order give the same bits, and both follow the reference to
+    the mixed path's gates."""
+    case = dambreak.make_case("small_batch")
+    skin = 0.01 * case.h
+    a = _sim(case, precision="mixed", skin=skin)
+    b = _sim(case, precision="mixed", skin=skin, use_graph=True)
+    refs = oracles_for(case)
+    a.prime()
+    b.prime()
+    for r in refs:
+        r.prime()
+    for _ in range(4):
+        a.step(10)
+        b.step(10)
+    for r in refs:
+        r.step(40)
+    ha, hb = a.host(), b.host()
+    for k in ("x", "v", "a", "rho", "dt", "id", "count"):
+        assert np.array_equal(ha[k], hb[k]), k
+    assert a.cell_builds() == b.cell_builds() > 1
+    for bi, r in enumerate(refs):
+        g = gpu_instance_view(a, ha, bi)
+        rv = oracle_view(r)
+        e = errors(g, rv, case.instances[bi].fluid)
+        assert e["rho"] < 1e-5 and e["v"] < 5e-2, (bi, e)
+        # counts come from FP32 r^2 on the mixed path
+        assert np.count_nonzero(g["count"] != rv["count"]) <= 1e-3 * r.n
+    assert a.poll_errors() == 0 and b.poll_errors() == 0
+    a.close()
+    b.close()
+
+
+def test_skin_matches_no_skin_run():
+    """With and without a skin a step sums the same pairs (in another order):
+    after 200 steps the states differ by summation rounding only."""
+    case = dambreak.make_case("tiny_3d")
+    a = _sim(case)
+    b = _sim(case, skin=0.1 * case.h)
+    a.prime()
+    b.prime()
+    a.step(200)
+    b.step(200)
+    ha, hb = a.host(), b.host()
+    _same_run(case, ha, hb)
+    assert 1 < b.cell_builds() < 201
+    a.close()
+    b.close()
+
+
+def test_skin_rejects_stage_calls():
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case("tiny_2d")
+    sim = _sim(case, skin=0.2 * case.h)
+    sim.prime()
+    for fn in (sph.sph_build_cells, sph.sph_density, sph.sph_forces):
+        with pytest.raises(sph.SphError, match="UNSUPPORTED"):
+            fn(sim.ctx)
+    with pytest.raises(sph.SphError, match="UNSUPPORTED"):
+        sph.sph_integrate(sim.ctx, 1)
+    sim.step(3)
+    assert sim.steps_done == 3
+    sim.close()
+
+
+@pytest.mark.slow
+def test_skin_full_size_c2_against_no_skin():
+    """The 2.0 M-particle 3D dam break in the benchmark's launch configuration
+    with a skin of 0.2 h: 50 steps against the same run without a skin (whose
+    one-step parity with the reference is checked elsewhere), bit-exact counts
+    and summation-rounding differences in the state."""
+    case = dambreak.make_case("c2_3d")
+    a = _sim(case)
+    b = _sim(case, skin=0.2 * case.h)
+    a.prime()
+    b.prime()
+    a.step(50)
+    b.step(50)
+    ha, hb = a.host(), b.host()
+    assert a.poll_errors() == 0 and b.poll_errors() == 0
+    _same_run(case, ha, hb)
+    assert ha["diag"][0][12] == hb["diag"][0][12]
+    print("c2 skin builds", b.cell_builds(), "of 51")
+    a.close()
+    b.close()
