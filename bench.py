@@ -5,7 +5,11 @@ at dx = 0.01 in a 4 x 1 x 3 m box, 1.17 M wall particles), plain FP64 path,
 arrays re-sorted by cell every 20 steps, 500 timed steps.  A step is the whole
 hot path: half kick + drift + cell keys, cell scan, radix sort, (reorder),
 sweep records, density sweep, force sweep fused with the second half kick,
-and the FP64 reductions for dt and the diagnostics.
+and the FP64 reductions for dt and the diagnostics.  By default the cell
+table and the neighbour lists carry a Verlet skin of 0.1 h: the device
+rebuilds them only when the particles may have moved half the skin (the
+number of builds in the timed steps is reported), and the same steps are
+timed again without a skin.
 
 Prints one JSON line.  Besides the headline value it reports the roofline of
 the dominant kernel (algorithmic FLOPs per launch over its HIP-event time),
@@ -208,13 +212,17 @@ def main(argv=None):
     ap.add_argument("--list", type=int, default=0, help="neighbour-list capacity (-1: no list)")
     ap.add_argument("--prefetch", type=int, default=0, help="candidate records in flight (4 or 8)")
     ap.add_argument("--reorder-every", type=int, default=None)
-    ap.add_argument("--skin", type=float, default=0.0,
+    ap.add_argument("--skin", type=float, default=0.1,
                     help="Verlet skin in units of h (0: cells and lists rebuilt every step)")
+    ap.add_argument("--no-skin-leg", action="store_true",
+                    help="skip the second timing of the headline path without a skin")
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps of the CPU sample (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (PMC calibration)")
     args = ap.parse_args(argv)
 
+    if args.scheme == "dual":
+        args.skin = 0.0                # the dual scheme rebuilds every advection step
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               "here is single-GPU and multi-GPU sharding is not built", file=sys.stderr)
@@ -332,6 +340,24 @@ def main(argv=None):
         del sim2
         torch.cuda.empty_cache()
 
+    no_skin = None
+    if args.skin > 0 and not args.no_skin_leg and args.scheme == "wcsph":
+        # the same steps with the cell table and lists rebuilt every step
+        sim3, h3, secs3, stages3, flags3 = run_gpu(case, args.precision, args.steps, args.warmup,
+                                                   args.graph, timing=not args.graph,
+                                                   stage_steps=min(args.steps, 50),
+                                                   reorder_every=args.reorder_every,
+                                                   block=args.block, list_cap=args.list,
+                                                   prefetch=args.prefetch, skin_h=0.0)
+        v3 = n_fluid * args.steps / secs3 / 1e6
+        no_skin = {"value": round(v3, 3), "ms_per_step": round(secs3 * 1e3 / args.steps, 4),
+                   "stage_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages3.items() if n},
+                   "flags": int(flags3)}
+        log(f"{args.precision} without skin: {secs3 * 1e3 / args.steps:.3f} ms/step, {v3:.1f} M updates/s")
+        sim3.close()
+        del sim3
+        torch.cuda.empty_cache()
+
     cpu = None
     if args.cpu_steps > 0:
         _, cv, cores, csecs = cpu_baseline(case, args.cpu_steps, args.scheme)
@@ -361,7 +387,7 @@ def main(argv=None):
                    "prefetch": args.prefetch or 8, "scheme": args.scheme,
                    "skin_h": args.skin},
         "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
-        "compare": other, "flags": int(flags), **extra,
+        "compare": other, "no_skin": no_skin, "flags": int(flags), **extra,
     }
     print(json.dumps(out), flush=True)
     return 0
