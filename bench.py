@@ -34,6 +34,7 @@ import numpy as np  # noqa: E402
 METRIC = "M particle-updates/s (3D WCSPH step) + achieved HBM GB/s vs FP64 path"
 FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
 HBM_PEAK_GBS = 8000.0
+CLOCK_HZ, N_CU = 2.4e9, 256
 
 # FP64 flops per candidate test and per neighbour pair (viscosity excluded:
 # it runs on approaching pairs only, so leaving it out keeps the count a
@@ -126,6 +127,25 @@ def load_traffic(workload, precision, kernel):
     if rec.get("source_hash") != kernel_source_hash() or "hbm_bytes_per_launch" not in rec:
         return None
     return float(rec["hbm_bytes_per_launch"])
+
+
+def load_l1(workload, precision, kernel):
+    """L1 (TCP) accesses per launch of a sweep from a committed rocprofv3 summary
+    taken on the current kernel sources (else None)."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"l1_{workload}_{precision}_tcp.md")
+    if not os.path.exists(path):
+        return None
+    acc, hsh = None, None
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^- (\w+) l1_accesses_per_launch: ([0-9.e+-]+)", line)
+            if m and m.group(1) == kernel:
+                acc = float(m.group(2))
+            m = re.match(r"^- source_hash: `([0-9a-f]+)`", line)
+            if m:
+                hsh = m.group(1)
+    return acc if hsh == kernel_source_hash() else None
 
 
 def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
@@ -292,6 +312,13 @@ def main(argv=None):
                     "candidates": int(cands), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
             if traffic:
                 roof["hbm_gbs"] = round(traffic / avg_s / 1e9, 1)
+            # what bounds the list walks: L1 tag lookups, about one cache
+            # access per clock per CU at most
+            acc = load_l1(args.case, args.precision + ("_skin" if args.skin else ""), name)
+            if acc:
+                per = acc / (avg_s * CLOCK_HZ * N_CU)
+                roof["l1"] = {"accesses_per_launch": acc, "per_clock_per_cu": round(per, 3),
+                              "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
         else:
             roof = {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": None, "traffic": None, "avg_ms": round(avg_s * 1e3, 4)}

@@ -18,6 +18,18 @@ namespace sphx {
 // Neighbour-list entries, 32 bits: source slot in bits 0..24; on the mixed path
 // the source cell's offset from the target cell in bits 25..30 (two bits per
 // axis, offset + 1); wall flag in bit 31.
+// Skin walks: run the walk of a step without a build in a kernel of its own,
+// free of the candidate-test code and its registers.
+constexpr bool kSkinSplitWalk = true;
+// List entries in flight per lane: in the skin's walk-only density kernel and
+// in the force walk.  Deep prefetch beats occupancy in these L1-bound walks:
+// measured on the 2.0 M-particle 3D dam break, 16 entries in flight at 2 waves
+// per SIMD (FP64) are faster than 8 at 3 or 4 at 5.
+template <int DIM, bool MIXED> constexpr int skin_walk_u() { return 16; }
+template <int DIM, bool MIXED> constexpr int force_walk_u() { return MIXED && DIM == 3 ? 16 : 8; }
+template <bool MIXED> constexpr int fused_walk_u() { return MIXED ? 8 : 4; }   // after the candidate tests
+constexpr int kDualWalkU = 4;          // the sub-step sweeps of the dual scheme (FP64): 8 was slower
+
 constexpr int kSlotBits = 25;
 constexpr unsigned kSlotMask = (1u << kSlotBits) - 1u;
 constexpr unsigned kWallBit = 0x80000000u;
@@ -592,7 +604,8 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
 }
 
 // Phase 2: fn(wall, s, r, r2, A_j, B_j) for the first m (<= cap) entries of
-// target k; the records of U entries are fetched before any of them is used.
+// target k; the records of U entries (U = 1, 2, 4, 8 or 16; above 4 a round
+// reads U / 4 quads) are fetched before any of them is used.
 // CHK: the list was built with a skin, so entries at 2h or beyond are skipped.
 template <int DIM, bool MIXED, int U, int NEED, bool CHK = false, class Fn>
 __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
@@ -601,16 +614,26 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
                                           const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
                                           const uint4 *__restrict__ nlist, int n, Fn &&fn)
 {
-    static_assert(U == 1 || U == 2 || U == 4, "entries come in quads");
+    static_assert(U == 1 || U == 2 || U == 4 || U == 8 || U == 16, "entries come in quads");
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
+    constexpr int QN = U > 4 ? U / 4 : 1;      // quads per round
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
-    for (int q0 = 0; q0 < m; q0 += 4) {
-        const uint4 quad = nlist[(int64_t)(q0 >> 2) * n + k];
-        const unsigned eq[4] = {quad.x, quad.y, quad.z, quad.w};
+    for (int q0 = 0; q0 < m; q0 += 4 * QN) {
+        unsigned eq[4 * QN];
 #pragma unroll
-        for (int h = 0; h < 4; h += U) {
+        for (int g = 0; g < QN; ++g) {
+            // a second quad past the end is not read (its entries are >= m)
+            uint4 quad = make_uint4(0u, 0u, 0u, 0u);
+            if (g == 0 || q0 + 4 * g < m) quad = nlist[(int64_t)((q0 >> 2) + g) * n + k];
+            eq[4 * g] = quad.x;
+            eq[4 * g + 1] = quad.y;
+            eq[4 * g + 2] = quad.z;
+            eq[4 * g + 3] = quad.w;
+        }
+#pragma unroll
+        for (int h = 0; h < 4 * QN; h += U) {
             v4 A[U], B[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -662,7 +685,9 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
 // LIST = 0: direct search.  LIST = 1: build the list, then walk it.  LIST = 2
 // (Verlet skin): build the list with radius 2h + skin when the previous
 // step's reduction asked for a rebuild (*gate != 0), else walk the list of the
-// last build; entries at 2h or beyond are skipped.
+// last build; entries at 2h or beyond are skipped.  LIST = 3: that walk alone,
+// in a kernel of its own (launched after LIST = 2; each returns at once on the
+// steps that belong to the other).
 template <int DIM, bool MIXED, int LIST, int PF>
 __global__ __launch_bounds__(kMaxBlock) void k_density(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
@@ -677,6 +702,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     using real = typename V::real;
     using v4 = typename V::v4;
     constexpr int NEED = DIM == 3 ? NEED_VEL : NEED_NONE;
+    // split skin walks: LIST = 2 runs on build steps only, LIST = 3 (walk
+    // only) on the others
+    if constexpr (LIST == 2 && kSkinSplitWalk) {
+        if (*gate == 0) return;
+    }
+    if constexpr (LIST == 3) {
+        if (*gate != 0) return;
+    }
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     if (k >= ch.end) return;
@@ -707,7 +740,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         drho += vr * F;
         ++cnt;
     };
-    if constexpr (LIST) {
+    if constexpr (LIST == 3) {
+        const int m = lcount[k];
+        if (m <= cap) walk_list<DIM, MIXED, skin_walk_u<DIM, MIXED>(), NEED, true>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+        else for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+    } else if constexpr (LIST) {
         float ci[3];
         if constexpr (MIXED) {
             ci[0] = pi[0]; ci[1] = pi[1]; ci[2] = pi[2];
@@ -727,7 +764,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
             m = lcount[k];
         }
         if (m <= cap) {
-            walk_list<DIM, MIXED, 4, NEED, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+            walk_list<DIM, MIXED, fused_walk_u<MIXED>(), NEED, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
         } else {
             if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -771,6 +808,7 @@ static void density_variant(const SimConst &sc, const Dev &d, int use_dt, hipStr
     else if (d.gate) {
         if (d.prefetch == 4) density_dispatch<DIM, MIXED, 2, 4>(sc, d, use_dt, s);
         else density_dispatch<DIM, MIXED, 2, 8>(sc, d, use_dt, s);
+        if (kSkinSplitWalk) density_dispatch<DIM, MIXED, 3, 4>(sc, d, use_dt, s);
     } else if (d.prefetch == 4) density_dispatch<DIM, MIXED, 1, 4>(sc, d, use_dt, s);
     else density_dispatch<DIM, MIXED, 1, 8>(sc, d, use_dt, s);
 }
@@ -802,7 +840,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
-    constexpr int U = 4;                   // list entries in flight per lane
+    constexpr int U = force_walk_u<DIM, MIXED>();
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     const bool act = k < ch.end;
@@ -1108,7 +1146,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
-            if (m <= cap) walk_list<DIM, false, 4, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+            if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
             else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         } else {
             for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -1176,7 +1214,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const int lk = skey[k] - I.cell_base;
     if constexpr (LIST) {
         const int m = lcount[k];
-        if (m <= cap) walk_list<DIM, false, 4, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+        if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
         else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
     } else {
         for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
