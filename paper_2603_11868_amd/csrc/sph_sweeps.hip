@@ -21,6 +21,10 @@ namespace sphx {
 // Skin walks: run the walk of a step without a build in a kernel of its own,
 // free of the candidate-test code and its registers.
 constexpr bool kSkinSplitWalk = true;
+// FP64 list walks gather records cooperatively (walk_coop).
+constexpr bool kCoopWalk = true;
+// list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
+constexpr int kCoopRoundsDensity = 4, kCoopRoundsForce = 2, kCoopRoundsDual = 2;
 // List entries in flight per lane: in the skin's walk-only density kernel and
 // in the force walk.  Deep prefetch beats occupancy in these L1-bound walks:
 // measured on the 2.0 M-particle 3D dam break, 16 entries in flight at 2 waves
@@ -678,6 +682,106 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
     }
 }
 
+// Cooperative walk of the FP64 lists.  The walks are bound by L1 tag lookups:
+// with one record per lane, each 16-byte load instruction of a wave touches
+// about 64 cache lines.  Here the four lanes of a quad fetch the 16-byte parts
+// of each other's records: instruction i loads, on lane 4g + p, part p of the
+// record that lane 4g + i needs, so one instruction touches 16 lines for 16
+// whole records.  An LDS exchange (80-byte stride: no bank conflicts) then
+// hands every lane its own record.  Every lane of the wave must call this,
+// with m = 0 for a lane that has nothing to walk.
+// Value of lane 4 * (lane / 4) + I (DPP quad permutation); 0 from a disabled lane.
+template <int I>
+__device__ __forceinline__ unsigned quad_bcast(int v)
+{
+    return (unsigned)__builtin_amdgcn_mov_dpp(v, I * 0x55, 0xF, 0xF, true);
+}
+
+template <int DIM, int NEED, bool CHK, int R, class Fn>
+__device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m, const double *pi,
+                                          const dvec4 *__restrict__ rec,
+                                          const typename Rec<DIM, false>::wpos_t *__restrict__ wpos,
+                                          const uint4 *__restrict__ nlist, int n, Fn &&fn)
+{
+    using V = RV<DIM, false>;
+    // 16-byte parts a sweep needs, of a fluid record and of a wall record
+    constexpr int NP = DIM == 3 ? (NEED == NEED_ALL ? 4 : (NEED == NEED_VEL ? 3 : 2))
+                                : (NEED == NEED_ALL ? 3 : 2);
+    constexpr int NPW = DIM == 3 ? 2 : 1;
+    constexpr int WBYTES = DIM == 3 ? 32 : 16;
+    constexpr int STRIDE = 5;                         // dvec2 slots per record in LDS
+    constexpr int RS = 64 * STRIDE;                   // one round of a wave
+    __shared__ dvec2 xch[kMaxBlock / 64][RS];
+    dvec2 *X = xch[threadIdx.x >> 6];
+    const int lane = lane_id();
+    const int p = lane & 3;
+    const int qb = lane & ~3;
+    const char *recb = reinterpret_cast<const char *>(rec);
+    const char *wb = reinterpret_cast<const char *>(wpos);
+    int mmax = m;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off, 64));
+    const double cut2 = sc.cut2;
+    for (int q0 = 0; q0 < mmax; q0 += 4) {
+        uint4 quad = make_uint4(0u, 0u, 0u, 0u);
+        if (q0 < m) quad = nlist[(int64_t)(q0 >> 2) * n + k];
+        const unsigned eq[4] = {quad.x, quad.y, quad.z, quad.w};
+#pragma unroll
+        for (int h0 = 0; h0 < 4; h0 += R) {
+            // round h (list position q0 + h): lane qb + p fetches part p of
+            // the record of lane qb + i.  Every lane loads (a part it does not
+            // need comes from a valid address and is zeroed), so the loads of
+            // all R rounds are in flight together.
+            dvec2 raw[R][4];
+            bool use[R][4];
+#pragma unroll
+            for (int h = 0; h < R; ++h) {
+                // entry + 1, or 0 when there is none (bound_ctrl also gives 0)
+                const int v = q0 + h0 + h < m ? (int)(eq[h0 + h] + 1u) : 0;
+                const unsigned vq[4] = {quad_bcast<0>(v), quad_bcast<1>(v), quad_bcast<2>(v), quad_bcast<3>(v)};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const unsigned e = vq[i] - 1u;
+                    const uint32_t s = vq[i] != 0u ? (e & kSlotMask) : 0u;
+                    const bool wall = vq[i] != 0u && (e & kWallBit) != 0u;
+                    use[h][i] = vq[i] != 0u && p < (wall ? NPW : NP);
+                    const char *src = wall ? wb + s * (uint32_t)WBYTES + (p < NPW ? (uint32_t)p * 16u : 0u)
+                                           : recb + s * 64u + (uint32_t)p * 16u;
+                    raw[h][i] = *reinterpret_cast<const dvec2 *>(src);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < R; ++h) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const dvec2 d = use[h][i] ? raw[h][i] : dvec2{0.0, 0.0};
+                    X[(qb + i) * STRIDE + p] = d;
+                }
+                // LDS operations of one wave execute in order: the reads below
+                // see the stores above, and the next round's stores come after
+                // them; the barriers only keep the compiler from reordering
+                __builtin_amdgcn_wave_barrier();
+                if (q0 + h0 + h < m) {
+                    const unsigned e = eq[h0 + h];
+                    const dvec2 *mine = X + lane * STRIDE;
+                    const dvec2 p0 = mine[0], p1 = mine[1];
+                    const dvec2 p2 = NP > 2 ? mine[2] : dvec2{0.0, 0.0};
+                    const dvec2 p3 = NP > 3 ? mine[3] : dvec2{0.0, 0.0};
+                    dvec4 A, B;
+                    A.x = p0.x; A.y = p0.y; A.z = p1.x; A.w = p1.y;
+                    B.x = p2.x; B.y = p2.y; B.z = p3.x; B.w = p3.y;
+                    double pj[3], r[3];
+                    V::pos(A, pj);
+                    sub_vec<DIM>(pi, pj, r);
+                    const double r2 = norm2<DIM>(r);
+                    if (!CHK || r2 < cut2) fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, r2, A, B);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // density sweep
 // ---------------------------------------------------------------------------
@@ -710,14 +814,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     if constexpr (LIST == 3) {
         if (*gate != 0) return;
     }
+    // the cooperative walk needs every lane of the wave, targets or not
+    constexpr bool COOP = LIST != 0 && !MIXED && kCoopWalk;
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
-    if (k >= ch.end) return;
+    const bool act = k < ch.end;
+    if (!COOP && !act) return;
+    const int kk = act ? k : ch.begin;
     const int n = sc.N;
     const InstDev &I = inst[ch.inst];
-    const int lk = skey[k] - I.cell_base;
-    const v4 Ai = V::loadA(rec, k);
-    const v4 Bi = load_need<DIM, MIXED, NEED>(rec, k);
+    const int lk = skey[kk] - I.cell_base;
+    const v4 Ai = V::loadA(rec, kk);
+    const v4 Bi = load_need<DIM, MIXED, NEED>(rec, kk);
     real pi[3], vi[3];
     V::pos(Ai, pi);
     V::vel(Ai, Bi, vi);
@@ -740,7 +848,34 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         drho += vr * F;
         ++cnt;
     };
-    if constexpr (LIST == 3) {
+    if constexpr (COOP && LIST == 3) {
+        const int m = act ? lcount[k] : 0;
+        walk_coop<DIM, NEED, true, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        if (!act) return;
+    } else if constexpr (COOP) {
+        // candidate tests per target, then the cooperative walk with every lane
+        const bool build = LIST == 1 || *gate != 0;
+        int m = 0;
+        if (act) {
+            if (build) {
+                const typename Cand<DIM>::t cp = cpos[k];
+                float ci[3] = {cp.x, cp.y, 0.0f};
+                if constexpr (DIM == 3) ci[2] = cp.z;
+                m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+                                               nlist, cap, n);
+                lcount[k] = m;
+            } else {
+                m = lcount[k];
+            }
+        }
+        walk_coop<DIM, NEED, LIST == 2, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        if (act && m > cap) {
+            if (build) atomicOr(flags, 4u);
+            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        }
+        if (!act) return;
+    } else if constexpr (LIST == 3) {
         const int m = lcount[k];
         if (m <= cap) walk_list<DIM, MIXED, skin_walk_u<DIM, MIXED>(), NEED, true>(sc, k, m, pi, rec, wpos, nlist, n, pair);
         else for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -894,7 +1029,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
         }
         ++cnt;
     };
-    if (act) {
+    if constexpr (LIST && !MIXED && kCoopWalk) {
+        // every lane takes part in the cooperative walk
+        const int m = act ? lcount[k] : 0;
+        walk_coop<DIM, NEED_ALL, LIST == 2, kCoopRoundsForce>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        if (act && m > cap)
+            for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
+    } else if (act) {
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
@@ -1142,7 +1283,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
         }
         ++cnt;
     };
-    if (act) {
+    if constexpr (LIST && kCoopWalk) {
+        // every lane takes part in the cooperative walk
+        const int m = act ? lcount[k] : 0;
+        walk_coop<DIM, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        if (act && m > cap)
+            for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
+    } else if (act) {
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
@@ -1185,11 +1332,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const Chunk ch = map[blockIdx.x];
     if (sub >= nsub[ch.inst]) return;
     const int k = ch.begin + threadIdx.x;
-    if (k >= ch.end) return;
+    const bool act = k < ch.end;
+    if (!(LIST && kCoopWalk) && !act) return;
+    const int kk = act ? k : ch.begin;
     const int n = sc.N;
     const InstDev &I = inst[ch.inst];
-    const v4 Ai = V::loadA(rec, k);
-    const v4 Bi = V::loadB(rec, k);
+    const v4 Ai = V::loadA(rec, kk);
+    const v4 Bi = V::loadB(rec, kk);
     double pi[3], vi[3];
     V::pos(Ai, pi);
     V::vel(Ai, Bi, vi);
@@ -1211,8 +1360,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
         kernel_F(r2, sc.inv_h, sc.kF, F);
         sum += dot * F / q.rho_j;
     };
-    const int lk = skey[k] - I.cell_base;
-    if constexpr (LIST) {
+    const int lk = skey[kk] - I.cell_base;
+    if constexpr (LIST && kCoopWalk) {
+        const int m = act ? lcount[k] : 0;
+        walk_coop<DIM, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        if (!act) return;
+    } else if constexpr (LIST) {
         const int m = lcount[k];
         if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
         else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
