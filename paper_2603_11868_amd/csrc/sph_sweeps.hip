@@ -13,6 +13,8 @@
 // FP32 cell-offset copies (cpos, wcpos) for cheap candidate tests.
 #include "sph_step_common.h"
 
+#include <type_traits>
+
 namespace sphx {
 
 // Neighbour-list entries, 32 bits: source slot in bits 0..24; on the mixed path
@@ -21,10 +23,13 @@ namespace sphx {
 // Skin walks: run the walk of a step without a build in a kernel of its own,
 // free of the candidate-test code and its registers.
 constexpr bool kSkinSplitWalk = true;
-// FP64 list walks gather records cooperatively (walk_coop).
+// List walks gather records cooperatively (walk_coop): FP64, and the mixed
+// path in 3D (a 2D mixed wall record is 8 bytes, smaller than a part).
 constexpr bool kCoopWalk = true;
+template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk && (!MIXED || DIM == 3); }
 // list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
-constexpr int kCoopRoundsDensity = 4, kCoopRoundsForce = 2, kCoopRoundsDual = 2;
+constexpr int kCoopRoundsDensity = 4, kCoopRoundsDual = 2;
+template <bool MIXED> constexpr int coop_rounds_force() { return MIXED ? 4 : 2; }
 // List entries in flight per lane: in the skin's walk-only density kernel and
 // in the force walk.  Deep prefetch beats occupancy in these L1-bound walks:
 // measured on the 2.0 M-particle 3D dam break, 16 entries in flight at 2 waves
@@ -682,98 +687,125 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
     }
 }
 
-// Cooperative walk of the FP64 lists.  The walks are bound by L1 tag lookups:
-// with one record per lane, each 16-byte load instruction of a wave touches
-// about 64 cache lines.  Here the four lanes of a quad fetch the 16-byte parts
-// of each other's records: instruction i loads, on lane 4g + p, part p of the
-// record that lane 4g + i needs, so one instruction touches 16 lines for 16
-// whole records.  An LDS exchange (80-byte stride: no bank conflicts) then
-// hands every lane its own record.  Every lane of the wave must call this,
-// with m = 0 for a lane that has nothing to walk.
-// Value of lane 4 * (lane / 4) + I (DPP quad permutation); 0 from a disabled lane.
-template <int I>
-__device__ __forceinline__ unsigned quad_bcast(int v)
+// Cooperative list walk.  The walks are bound by L1 tag lookups: with one
+// record per lane, each 16-byte load instruction of a wave touches about 64
+// cache lines.  Here the G lanes of a group (G = 16-byte parts of a record:
+// 4 for FP64, 2 for the mixed path's 32-byte records) fetch the parts of each
+// other's records: instruction i loads, on lane G g + p, part p of the record
+// that lane G g + i needs, so one instruction touches 64 / G lines for whole
+// records.  An LDS exchange (stride G + 1 parts: no bank conflicts) then hands
+// every lane its own record.  All loads of R list positions are issued before
+// any is used; an unneeded part is loaded from a valid address and zeroed.
+// Every lane of the wave must call this, with m = 0 for a lane with nothing to
+// walk.
+
+// Value of lane G * (lane / G) + I within groups of G = 4 or 2 lanes (DPP
+// quad permutation); 0 from a disabled lane.
+template <int G, int I>
+__device__ __forceinline__ unsigned group_bcast(int v)
 {
-    return (unsigned)__builtin_amdgcn_mov_dpp(v, I * 0x55, 0xF, 0xF, true);
+    constexpr int ctrl = G == 4 ? I * 0x55 : (I | (I << 2) | ((2 + I) << 4) | ((2 + I) << 6));
+    return (unsigned)__builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
 }
 
-template <int DIM, int NEED, bool CHK, int R, class Fn>
-__device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m, const double *pi,
-                                          const dvec4 *__restrict__ rec,
-                                          const typename Rec<DIM, false>::wpos_t *__restrict__ wpos,
+template <int DIM, bool MIXED, int NEED, bool CHK, int R, class Fn>
+__device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
+                                          const typename RV<DIM, MIXED>::real *pi,
+                                          const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
+                                          const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
                                           const uint4 *__restrict__ nlist, int n, Fn &&fn)
 {
-    using V = RV<DIM, false>;
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    using v4 = typename V::v4;
+    static_assert(!MIXED || DIM == 3, "a mixed 2D wall record is smaller than a part");
+    using part_t = std::conditional_t<MIXED, fvec4, dvec2>;     // 16 bytes
+    constexpr int G = MIXED ? 2 : 4;
     // 16-byte parts a sweep needs, of a fluid record and of a wall record
-    constexpr int NP = DIM == 3 ? (NEED == NEED_ALL ? 4 : (NEED == NEED_VEL ? 3 : 2))
-                                : (NEED == NEED_ALL ? 3 : 2);
-    constexpr int NPW = DIM == 3 ? 2 : 1;
-    constexpr int WBYTES = DIM == 3 ? 32 : 16;
-    constexpr int STRIDE = 5;                         // dvec2 slots per record in LDS
-    constexpr int RS = 64 * STRIDE;                   // one round of a wave
-    __shared__ dvec2 xch[kMaxBlock / 64][RS];
-    dvec2 *X = xch[threadIdx.x >> 6];
+    constexpr int NP = MIXED ? (NEED != NEED_NONE ? 2 : 1)
+                             : (DIM == 3 ? (NEED == NEED_ALL ? 4 : (NEED == NEED_VEL ? 3 : 2))
+                                         : (NEED == NEED_ALL ? 3 : 2));
+    constexpr int NPW = (MIXED || DIM == 2) ? 1 : 2;
+    constexpr uint32_t RBYTES = MIXED ? 32u : 64u;
+    constexpr uint32_t WBYTES = sizeof(typename V::wpos_t);
+    constexpr int STRIDE = G + 1;                     // parts per record in LDS
+    constexpr int RS = 64 * STRIDE;
+    __shared__ part_t xch[kMaxBlock / 64][RS];
+    part_t *X = xch[threadIdx.x >> 6];
     const int lane = lane_id();
-    const int p = lane & 3;
-    const int qb = lane & ~3;
+    const int p = lane & (G - 1);
+    const int gb = lane & ~(G - 1);
     const char *recb = reinterpret_cast<const char *>(rec);
     const char *wb = reinterpret_cast<const char *>(wpos);
+    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
+    const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
     int mmax = m;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off, 64));
-    const double cut2 = sc.cut2;
     for (int q0 = 0; q0 < mmax; q0 += 4) {
         uint4 quad = make_uint4(0u, 0u, 0u, 0u);
         if (q0 < m) quad = nlist[(int64_t)(q0 >> 2) * n + k];
         const unsigned eq[4] = {quad.x, quad.y, quad.z, quad.w};
 #pragma unroll
         for (int h0 = 0; h0 < 4; h0 += R) {
-            // round h (list position q0 + h): lane qb + p fetches part p of
-            // the record of lane qb + i.  Every lane loads (a part it does not
-            // need comes from a valid address and is zeroed), so the loads of
-            // all R rounds are in flight together.
-            dvec2 raw[R][4];
-            bool use[R][4];
+            part_t raw[R][G];
+            bool use[R][G];
 #pragma unroll
             for (int h = 0; h < R; ++h) {
                 // entry + 1, or 0 when there is none (bound_ctrl also gives 0)
                 const int v = q0 + h0 + h < m ? (int)(eq[h0 + h] + 1u) : 0;
-                const unsigned vq[4] = {quad_bcast<0>(v), quad_bcast<1>(v), quad_bcast<2>(v), quad_bcast<3>(v)};
+                unsigned vg[G];
+                vg[0] = group_bcast<G, 0>(v);
+                vg[1] = group_bcast<G, 1>(v);
+                if constexpr (G == 4) {
+                    vg[2] = group_bcast<G, 2>(v);
+                    vg[3] = group_bcast<G, 3>(v);
+                }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const unsigned e = vq[i] - 1u;
-                    const uint32_t s = vq[i] != 0u ? (e & kSlotMask) : 0u;
-                    const bool wall = vq[i] != 0u && (e & kWallBit) != 0u;
-                    use[h][i] = vq[i] != 0u && p < (wall ? NPW : NP);
-                    const char *src = wall ? wb + s * (uint32_t)WBYTES + (p < NPW ? (uint32_t)p * 16u : 0u)
-                                           : recb + s * 64u + (uint32_t)p * 16u;
-                    raw[h][i] = *reinterpret_cast<const dvec2 *>(src);
+                for (int i = 0; i < G; ++i) {
+                    const unsigned e = vg[i] - 1u;
+                    const uint32_t s = vg[i] != 0u ? (e & kSlotMask) : 0u;
+                    const bool wall = vg[i] != 0u && (e & kWallBit) != 0u;
+                    use[h][i] = vg[i] != 0u && p < (wall ? NPW : NP);
+                    const char *src = wall ? wb + s * WBYTES + (p < NPW ? (uint32_t)p * 16u : 0u)
+                                           : recb + s * RBYTES + (uint32_t)p * 16u;
+                    raw[h][i] = *reinterpret_cast<const part_t *>(src);
                 }
             }
 #pragma unroll
             for (int h = 0; h < R; ++h) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const dvec2 d = use[h][i] ? raw[h][i] : dvec2{0.0, 0.0};
-                    X[(qb + i) * STRIDE + p] = d;
-                }
+                for (int i = 0; i < G; ++i) X[(gb + i) * STRIDE + p] = use[h][i] ? raw[h][i] : part_t{};
                 // LDS operations of one wave execute in order: the reads below
-                // see the stores above, and the next round's stores come after
-                // them; the barriers only keep the compiler from reordering
+                // see the stores above, and the next stores come after them;
+                // the barriers only keep the compiler from reordering them
                 __builtin_amdgcn_wave_barrier();
                 if (q0 + h0 + h < m) {
                     const unsigned e = eq[h0 + h];
-                    const dvec2 *mine = X + lane * STRIDE;
-                    const dvec2 p0 = mine[0], p1 = mine[1];
-                    const dvec2 p2 = NP > 2 ? mine[2] : dvec2{0.0, 0.0};
-                    const dvec2 p3 = NP > 3 ? mine[3] : dvec2{0.0, 0.0};
-                    dvec4 A, B;
-                    A.x = p0.x; A.y = p0.y; A.z = p1.x; A.w = p1.y;
-                    B.x = p2.x; B.y = p2.y; B.z = p3.x; B.w = p3.y;
-                    double pj[3], r[3];
+                    const part_t *mine = X + lane * STRIDE;
+                    v4 A, B;
+                    if constexpr (MIXED) {
+                        A = mine[0];
+                        B = NP > 1 ? mine[1] : fvec4{};
+                    } else {
+                        const dvec2 p0 = mine[0], p1 = mine[1];
+                        const dvec2 p2 = NP > 2 ? mine[2] : dvec2{0.0, 0.0};
+                        const dvec2 p3 = NP > 3 ? mine[3] : dvec2{0.0, 0.0};
+                        A.x = p0.x; A.y = p0.y; A.z = p1.x; A.w = p1.y;
+                        B.x = p2.x; B.y = p2.y; B.z = p3.x; B.w = p3.y;
+                    }
+                    real pj[3], t[3], r[3];
                     V::pos(A, pj);
-                    sub_vec<DIM>(pi, pj, r);
-                    const double r2 = norm2<DIM>(r);
+                    if constexpr (MIXED) {
+                        const int ox = (int)((e >> kSlotBits) & 3u) - 1;
+                        const int oy = (int)((e >> (kSlotBits + 2)) & 3u) - 1;
+                        const int oz = (int)((e >> (kSlotBits + 4)) & 3u) - 1;
+                        shift_target<DIM, true>(pi, ox, oy, oz, cs, t);
+                    } else {
+                        shift_target<DIM, false>(pi, 0, 0, 0, cs, t);
+                    }
+                    sub_vec<DIM>(t, pj, r);
+                    const real r2 = norm2<DIM>(r);
                     if (!CHK || r2 < cut2) fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, r2, A, B);
                 }
                 __builtin_amdgcn_wave_barrier();
@@ -815,7 +847,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         if (*gate != 0) return;
     }
     // the cooperative walk needs every lane of the wave, targets or not
-    constexpr bool COOP = LIST != 0 && !MIXED && kCoopWalk;
+    // (the mixed walk-only kernel is as fast with sixteen entries per lane in flight)
+    constexpr bool COOP = LIST != 0 && use_coop<DIM, MIXED>() && !(MIXED && LIST == 3);
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     const bool act = k < ch.end;
@@ -850,7 +883,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     };
     if constexpr (COOP && LIST == 3) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, NEED, true, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (COOP) {
@@ -859,9 +892,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         int m = 0;
         if (act) {
             if (build) {
-                const typename Cand<DIM>::t cp = cpos[k];
-                float ci[3] = {cp.x, cp.y, 0.0f};
-                if constexpr (DIM == 3) ci[2] = cp.z;
+                float ci[3];
+                if constexpr (MIXED) {
+                    ci[0] = pi[0]; ci[1] = pi[1]; ci[2] = pi[2];
+                } else {
+                    const typename Cand<DIM>::t cp = cpos[k];
+                    ci[0] = cp.x; ci[1] = cp.y;
+                    if constexpr (DIM == 3) ci[2] = cp.z;
+                    else ci[2] = 0.0f;
+                }
                 m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
                                                nlist, cap, n);
                 lcount[k] = m;
@@ -869,7 +908,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
                 m = lcount[k];
             }
         }
-        walk_coop<DIM, NEED, LIST == 2, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
         if (act && m > cap) {
             if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -1029,10 +1068,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
         }
         ++cnt;
     };
-    if constexpr (LIST && !MIXED && kCoopWalk) {
+    if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, NEED_ALL, LIST == 2, kCoopRoundsForce>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, coop_rounds_force<MIXED>()>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
@@ -1286,7 +1325,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     if constexpr (LIST && kCoopWalk) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
@@ -1363,7 +1402,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const int lk = skey[kk] - I.cell_base;
     if constexpr (LIST && kCoopWalk) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (LIST) {
