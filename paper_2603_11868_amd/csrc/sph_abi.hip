@@ -175,7 +175,7 @@ void collect_times(sph_ctx *c)
 
 // bytes of one fluid sweep record (two 4-vectors) and of one wall record
 int rec_bytes(bool mixed) { return mixed ? 32 : 64; }
-int wall_rec_bytes(int dim, bool mixed) { return mixed ? (dim == 3 ? 16 : 8) : (dim == 3 ? 32 : 16); }
+int wall_rec_bytes(int dim, bool mixed) { return mixed ? 16 : (dim == 3 ? 32 : 16); }
 
 void build_layout(sph_ctx *c)
 {

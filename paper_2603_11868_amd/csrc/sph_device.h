@@ -71,7 +71,7 @@ struct SimConst {
 template <int DIM, bool MIXED> struct Rec;
 template <> struct Rec<2, false> { using v4 = dvec4; using v2 = dvec2; using wpos_t = dvec2; using real = double; };
 template <> struct Rec<3, false> { using v4 = dvec4; using v2 = dvec2; using wpos_t = dvec4; using real = double; };
-template <> struct Rec<2, true>  { using v4 = fvec4; using v2 = fvec2; using wpos_t = fvec2; using real = float; };
+template <> struct Rec<2, true>  { using v4 = fvec4; using v2 = fvec2; using wpos_t = fvec4; using real = float; };
 template <> struct Rec<3, true>  { using v4 = fvec4; using v2 = fvec2; using wpos_t = fvec4; using real = float; };
 
 // ---- wave64 primitives ------------------------------------------------------

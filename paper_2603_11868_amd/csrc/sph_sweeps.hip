@@ -23,10 +23,9 @@ namespace sphx {
 // Skin walks: run the walk of a step without a build in a kernel of its own,
 // free of the candidate-test code and its registers.
 constexpr bool kSkinSplitWalk = true;
-// List walks gather records cooperatively (walk_coop): FP64, and the mixed
-// path in 3D (a 2D mixed wall record is 8 bytes, smaller than a part).
+// List walks gather records cooperatively (walk_coop).
 constexpr bool kCoopWalk = true;
-template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk && (!MIXED || DIM == 3); }
+template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
 // list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
 constexpr int kCoopRoundsDensity = 4, kCoopRoundsDual = 2;
 template <bool MIXED> constexpr int coop_rounds_force() { return MIXED ? 4 : 2; }
@@ -296,6 +295,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_wall_pack(
     w.y = MIXED ? (real)o[1] : (real)xj[1];
     if constexpr (DIM == 3) {
         w.z = MIXED ? (real)o[2] : (real)xj[2];
+        w.w = 0;
+    } else if constexpr (MIXED) {
+        w.z = 0;                           // 16-byte record: zero velocity
         w.w = 0;
     }
     wpos[k] = w;
@@ -718,7 +720,6 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
-    static_assert(!MIXED || DIM == 3, "a mixed 2D wall record is smaller than a part");
     using part_t = std::conditional_t<MIXED, fvec4, dvec2>;     // 16 bytes
     constexpr int G = MIXED ? 2 : 4;
     // 16-byte parts a sweep needs, of a fluid record and of a wall record
