@@ -27,10 +27,36 @@ __device__ __forceinline__ double kick(double v, double a, double dt)
     return v + 0.5 * dt * a;
 }
 
-// |r| from r^2: correctly rounded in FP64; in FP32 the hardware square root
+// |r| from r^2 and reciprocals in the pair loops.  FP64: the hardware
+// estimates refined by Newton (Goldschmidt) steps to within about 1 ulp, with
+// none of the range scaling a general square root or IEEE division needs
+// (r^2 here is 0 or a normal number below (2h)^2; divisors are densities and
+// sums of positive terms).  FP32: the hardware square root and reciprocal
 // (1 ulp), which the mixed path's tolerance covers.
-__device__ __forceinline__ double root(double r2) { return sqrt(r2); }
+__device__ __forceinline__ double root(double r2)
+{
+    const double y = __builtin_amdgcn_rsq(r2);
+    double g = r2 * y, hh = 0.5 * y;
+    const double e = fma(-g, hh, 0.5);
+    g = fma(g, e, g);
+    hh = fma(hh, e, hh);
+    double d = fma(-g, g, r2);
+    g = fma(d, hh, g);
+    d = fma(-g, g, r2);
+    g = fma(d, hh, g);
+    return r2 > 0.0 ? g : 0.0;
+}
 __device__ __forceinline__ float root(float r2) { return __builtin_amdgcn_sqrtf(r2); }
+
+__device__ __forceinline__ double recip(double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-b, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float b) { return __builtin_amdgcn_rcpf(b); }
 
 // Wendland C2: W = kW t^4 (2q + 1), F = (1/r) dW/dr = kF t^3, t = 1 - q/2.
 template <class real>

@@ -1057,8 +1057,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
         real visc = 0;
         if (vr < (real)0) {
             const real den = (real)0.5 * (rho_i + rho_j) * (r2 + eps_h2);
-            if constexpr (MIXED) visc = -visc_a * vr * __builtin_amdgcn_rcpf(den);
-            else visc = -visc_a * vr / den;
+            visc = -visc_a * vr * recip(den);
         }
         const real coef = (P_i + P_j + visc) * F;
         const real coef_ff = wall ? (real)0 : coef;
@@ -1262,8 +1261,8 @@ __device__ __forceinline__ void dual_pair(const SimConst &sc, bool wall, const d
     p_m = p_m < 0.0 ? 0.0 : p_m;
     q.rho_j = wall ? rho_i : V::rho(Bj);
     q.p_j = wall ? p_m : V::P(Bj);
-    const double rr = sqrt(r2);
-    const double inv = rr > 0.0 ? 1.0 / rr : 0.0;
+    const double rr = root(r2);
+    const double inv = rr > 0.0 ? recip(rr) : 0.0;
     q.ul = 0.0;
     q.ur = 0.0;
 #pragma unroll
@@ -1300,7 +1299,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     V::pos(Ai, pi);
     V::vel(Ai, Bi, vi);
     const double rho_i = V::rho(Bi), p_i = V::P(Bi);
-    const double c0 = I.c0;
+    const double c0 = I.c0, inv_c0 = 1.0 / c0;
     double acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
     int cnt = 0;
     auto pair = [&](bool wall, int, const double *r, double r2, const v4 &Aj, const v4 &Bj)
@@ -1309,12 +1308,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
         dual_pair<DIM>(sc, wall, r, r2, vi, rho_i, p_i, Aj, Bj, q);
         const double zl = rho_i * c0, zr = q.rho_j * c0;
         const double du = q.ul - q.ur;
-        double beta = sc.eta * (du > 0.0 ? du : 0.0) / c0;
+        double beta = sc.eta * (du > 0.0 ? du : 0.0) * inv_c0;
         beta = beta > 1.0 ? 1.0 : beta;
-        const double ps = (zl * q.p_j + zr * p_i + zl * zr * beta * du) / (zl + zr);
+        const double ps = (zl * q.p_j + zr * p_i + zl * zr * beta * du) * recip(zl + zr);
         double F;
         kernel_F(r2, sc.inv_h, sc.kF, F);
-        const double coef = 2.0 * ps / (rho_i * q.rho_j) * F;
+        const double coef = 2.0 * ps * recip(rho_i * q.rho_j) * F;
         const double coef_ff = wall ? 0.0 : coef;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
@@ -1390,15 +1389,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
         DualPair<DIM> q;
         dual_pair<DIM>(sc, wall, r, r2, vi, rho_i, p_i, Aj, Bj, q);
         const double zl = rho_i * c0, zr = q.rho_j * c0, zs = zl + zr;
+        const double izs = recip(zs);
         double dot = 0.0;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const double dv = zr * (vi[c] - q.vj[c]) / zs + (p_i - q.p_j) / zs * q.e[c];
+            const double dv = zr * (vi[c] - q.vj[c]) * izs + (p_i - q.p_j) * izs * q.e[c];
             dot += dv * r[c];
         }
         double F;
         kernel_F(r2, sc.inv_h, sc.kF, F);
-        sum += dot * F / q.rho_j;
+        sum += dot * F * recip(q.rho_j);
     };
     const int lk = skey[kk] - I.cell_base;
     if constexpr (LIST && kCoopWalk) {
