@@ -148,6 +148,25 @@ def load_l1(workload, precision, kernel):
     return acc if hsh == kernel_source_hash() else None
 
 
+def load_valu(workload, precision, kernel):
+    """VALU instructions (wave64) per launch of a sweep from a committed
+    rocprofv3 summary taken on the current kernel sources (else None)."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}_{precision}_sq.md")
+    if not os.path.exists(path):
+        return None
+    val, hsh = None, None
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^- (\w+) valu_insts_per_launch: ([0-9.e+-]+)", line)
+            if m and m.group(1) == kernel:
+                val = float(m.group(2))
+            m = re.match(r"^- source_hash: `([0-9a-f]+)`", line)
+            if m:
+                hsh = m.group(1)
+    return val if hsh == kernel_source_hash() else None
+
+
 def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
             list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph", skin_h=0.0):
     import torch
@@ -299,6 +318,11 @@ def main(argv=None):
                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
                     "traffic": load_traffic(args.case, "dual", name), "flops_per_launch": float(flops),
                     "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
+            vi = load_valu(args.case, "dual", name)
+            if vi:
+                per = vi / (avg_s * CLOCK_HZ * N_CU)
+                roof["valu_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
+                                      "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
         elif name in ("density", "force"):
             # with a skin the candidates are tested at builds only
             build_frac = sim.timed_builds / args.steps
@@ -314,11 +338,19 @@ def main(argv=None):
                 roof["hbm_gbs"] = round(traffic / avg_s / 1e9, 1)
             # what bounds the list walks: L1 tag lookups, about one cache
             # access per clock per CU at most
-            acc = load_l1(args.case, args.precision + ("_skin" if args.skin else ""), name)
+            key = args.precision + ("_skin" if args.skin else "")
+            acc = load_l1(args.case, key, name)
             if acc:
                 per = acc / (avg_s * CLOCK_HZ * N_CU)
                 roof["l1"] = {"accesses_per_launch": acc, "per_clock_per_cu": round(per, 3),
                               "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
+            # VALU issue: a CU issues at most one wave64 VALU instruction per
+            # clock (4 SIMDs, 4 clocks each); FP64 and FP32 alike here
+            vi = load_valu(args.case, key, name)
+            if vi:
+                per = vi / (avg_s * CLOCK_HZ * N_CU)
+                roof["valu_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
+                                      "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
         else:
             roof = {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": None, "traffic": None, "avg_ms": round(avg_s * 1e3, 4)}

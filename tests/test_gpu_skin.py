@@ -164,3 +164,45 @@ def test_skin_full_size_c2_against_no_skin():
     print("c2 skin builds", b.cell_builds(), "of 51")
     a.close()
     b.close()
+
+
+def test_skin_edge_cases_empty_instance_single_particle_and_clamping():
+    """The batch of degenerate instances of the plain edge-case test (a lone
+    particle in free fall, an instance without fluid, particles outside the
+    tank whose keys are clamped) with a skin.  Clamped keys are counted at
+    builds only, so that diagnostic is not compared."""
+    from paper_2603_11868_amd import sph
+    dx = 0.05
+    i0 = dambreak.dam_break_instance(2, dx, (1.0, 1.0), (0.05, 0.05), 1)
+    i0.fluid = np.array([[0.5, 0.6]])
+    i1 = dambreak.dam_break_instance(2, dx, (0.5, 0.5), (0.0, 0.0), 2)
+    i2 = dambreak.dam_break_instance(2, dx, (0.5, 0.5), (0.2, 0.2), 3)
+    i2.fluid = i2.fluid.copy()
+    i2.fluid[0] = [-5.0, 0.1]
+    i2.fluid[1] = [0.1, 7.0]
+    for inst in (i0, i1, i2):
+        inst.c0 = 10.0
+    case = dambreak.Case("edge", 2, dx, 1.3 * dx, reorder_every=2, instances=[i0, i1, i2])
+    sim = _sim(case, skin=0.2 * case.h)
+    refs = oracles_for(case)
+    sim.prime()
+    for r in refs:
+        r.prime()
+    assert sim.poll_errors() & sph.SPH_FLAG_CLAMPED
+    sim.step(5)
+    for r in refs:
+        r.step(5)
+    h = sim.host()
+    for b, r in enumerate(refs):
+        g = gpu_instance_view(sim, h, b)
+        rv = oracle_view(r)
+        assert np.array_equal(g["count"], rv["count"]), b
+        if r.n:
+            assert np.abs(g["x"] - rv["x"]).max() < 1e-12
+            assert np.abs(g["v"] - rv["v"]).max() < 1e-9
+        assert g["dt"] == pytest.approx(rv["dt"], rel=1e-12)
+    g0 = gpu_instance_view(sim, h, 0)
+    t = g0["diag"][14]
+    assert g0["x"][0, 1] == pytest.approx(0.6 - 0.5 * 9.81 * t * t, abs=1e-12)
+    assert h["diag"][1][0] == 0.0 and h["diag"][1][2] == 0.0
+    sim.close()
