@@ -145,18 +145,25 @@ def test_skin_rejects_stage_calls():
 
 
 @pytest.mark.slow
-def test_skin_full_size_c2_against_no_skin():
+def test_skin_full_size_c2_against_reference_and_no_skin():
     """The 2.0 M-particle 3D dam break in the benchmark's launch configuration
-    with a skin of 0.2 h: 50 steps against the same run without a skin (whose
-    one-step parity with the reference is checked elsewhere), bit-exact counts
-    and summation-rounding differences in the state."""
+    (FP64, skin 0.1 h): two steps against the CPU reference particle by
+    particle (the second one walks the prime's lists), then 50 steps against
+    the same run without a skin: bit-exact counts and summation-rounding
+    differences in the state."""
     case = dambreak.make_case("c2_3d")
     a = _sim(case)
-    b = _sim(case, skin=0.2 * case.h)
+    b = _sim(case, skin=0.1 * case.h)
+    (r,) = oracles_for(case)
     a.prime()
     b.prime()
+    r.prime()
+    b.step(2)
+    r.step(2)
+    assert b.cell_builds() == 1
+    _compare(b, [r], case, 2, 1e-9)
     a.step(50)
-    b.step(50)
+    b.step(48)
     ha, hb = a.host(), b.host()
     assert a.poll_errors() == 0 and b.poll_errors() == 0
     _same_run(case, ha, hb)
