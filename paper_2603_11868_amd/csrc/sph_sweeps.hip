@@ -29,10 +29,11 @@ template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
 // list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
 constexpr int kCoopRoundsDensity = 4, kCoopRoundsDual = 2;
 template <bool MIXED> constexpr int coop_rounds_force() { return MIXED ? 4 : 2; }
-// List entries in flight per lane: in the skin's walk-only density kernel and
-// in the force walk.  Deep prefetch beats occupancy in these L1-bound walks:
-// measured on the 2.0 M-particle 3D dam break, 16 entries in flight at 2 waves
-// per SIMD (FP64) are faster than 8 at 3 or 4 at 5.
+// List entries in flight per lane in the per-lane walks (walk_list: the mixed
+// walk-only density kernel, and every walk when the cooperative gather is
+// off).  Deep prefetch beats occupancy in these L1-bound walks: measured on
+// the 2.0 M-particle 3D dam break, 16 entries in flight at 2 waves per SIMD
+// (FP64) were faster than 8 at 3 or 4 at 5.
 template <int DIM, bool MIXED> constexpr int skin_walk_u() { return 16; }
 template <int DIM, bool MIXED> constexpr int force_walk_u() { return MIXED && DIM == 3 ? 16 : 8; }
 template <bool MIXED> constexpr int fused_walk_u() { return MIXED ? 8 : 4; }   // after the candidate tests
@@ -689,9 +690,9 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
     }
 }
 
-// Cooperative list walk.  The walks are bound by L1 tag lookups: with one
-// record per lane, each 16-byte load instruction of a wave touches about 64
-// cache lines.  Here the G lanes of a group (G = 16-byte parts of a record:
+// Cooperative list walk.  Walks with one record per lane are bound by L1 tag
+// lookups: each 16-byte load instruction of a wave touches about 64 cache
+// lines.  Here the G lanes of a group (G = 16-byte parts of a record:
 // 4 for FP64, 2 for the mixed path's 32-byte records) fetch the parts of each
 // other's records: instruction i loads, on lane G g + p, part p of the record
 // that lane G g + i needs, so one instruction touches 64 / G lines for whole
@@ -736,8 +737,10 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     const int lane = lane_id();
     const int p = lane & (G - 1);
     const int gb = lane & ~(G - 1);
-    const char *recb = reinterpret_cast<const char *>(rec);
-    const char *wb = reinterpret_cast<const char *>(wpos);
+    // this lane's part of a record, and of a wall record (part 0 past its end)
+    const bool pNP = p < NP, pNPW = p < NPW;
+    const char *recbp = reinterpret_cast<const char *>(rec) + p * 16;
+    const char *wbp = reinterpret_cast<const char *>(wpos) + (pNPW ? p * 16 : 0);
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
     const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
     int mmax = m;
@@ -764,12 +767,12 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
                 }
 #pragma unroll
                 for (int i = 0; i < G; ++i) {
+                    const bool has = vg[i] != 0u;
                     const unsigned e = vg[i] - 1u;
-                    const uint32_t s = vg[i] != 0u ? (e & kSlotMask) : 0u;
-                    const bool wall = vg[i] != 0u && (e & kWallBit) != 0u;
-                    use[h][i] = vg[i] != 0u && p < (wall ? NPW : NP);
-                    const char *src = wall ? wb + s * WBYTES + (p < NPW ? (uint32_t)p * 16u : 0u)
-                                           : recb + s * RBYTES + (uint32_t)p * 16u;
+                    const uint32_t s = has ? (e & kSlotMask) : 0u;
+                    const bool wall = has && (e & kWallBit) != 0u;
+                    use[h][i] = has && (wall ? pNPW : pNP);
+                    const char *src = wall ? wbp + s * WBYTES : recbp + s * RBYTES;
                     raw[h][i] = *reinterpret_cast<const part_t *>(src);
                 }
             }
