@@ -302,6 +302,9 @@ sph_status sph_poll_errors(sph_ctx *ctx, uint32_t *flags, void *stream);
  * milliseconds and launch counts of up to `n` stages (names from
  * sph_stage_name) and, if reset != 0, clears them.  Synchronises `stream`. */
 sph_status sph_set_timing(sph_ctx *ctx, int32_t enable);
+/* The same for the stages whose bit (1 << stage index) is set in mask
+ * (0 = off): fewer events, less overhead in the timed steps. */
+sph_status sph_set_timing_mask(sph_ctx *ctx, uint32_t mask);
 sph_status sph_stage_times(sph_ctx *ctx, double *ms, int64_t *launches, int32_t n,
                            int32_t reset, void *stream);
 const char *sph_stage_name(int32_t stage);

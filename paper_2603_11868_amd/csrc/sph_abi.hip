@@ -111,8 +111,9 @@ struct sph_ctx {
     // graphs
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    // timing
+    // timing: events around the stages whose bit (1 << stage) is set
     bool timing = false;
+    uint32_t timing_mask = 0;
     struct Rec {
         int stage;
         hipEvent_t a, b;
@@ -144,7 +145,7 @@ struct StageTimer {
     hipEvent_t a = nullptr;
     StageTimer(sph_ctx *c_, int st, hipStream_t s_, bool on) : c(c_), stage(st), s(s_)
     {
-        if (on) {
+        if (on && ((c->timing_mask >> st) & 1u)) {
             a = take_event(c);
             if (a) (void)hipEventRecord(a, s);
         }
@@ -859,10 +860,19 @@ sph_status sph_poll_errors(sph_ctx *c, uint32_t *flags, void *stream)
     return SPH_OK;
 }
 
+sph_status sph_set_timing_mask(sph_ctx *c, uint32_t mask)
+{
+    if (!c) return fail(SPH_E_ARG, "null context");
+    c->timing_mask = mask & ((1u << ST_COUNT) - 1u);
+    c->timing = c->timing_mask != 0;
+    return SPH_OK;
+}
+
 sph_status sph_set_timing(sph_ctx *c, int32_t enable)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     c->timing = enable != 0;
+    c->timing_mask = enable != 0 ? (1u << ST_COUNT) - 1u : 0u;
     return SPH_OK;
 }
 

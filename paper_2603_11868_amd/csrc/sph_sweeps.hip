@@ -27,7 +27,7 @@ constexpr bool kSkinSplitWalk = true;
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
 // list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
-constexpr int kCoopRoundsDensity = 4, kCoopRoundsDual = 2;
+constexpr int kCoopRoundsDensity = 4, kCoopRoundsDual = 4;
 template <bool MIXED> constexpr int coop_rounds_force() { return MIXED ? 4 : 2; }
 // List entries in flight per lane in the per-lane walks (walk_list: the mixed
 // walk-only density kernel, and every walk when the cooperative gather is

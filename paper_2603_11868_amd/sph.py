@@ -36,7 +36,7 @@ SYMBOLS = ("sph_last_error", "sph_create", "sph_destroy", "sph_get_info", "sph_g
            "sph_workspace_size", "sph_bind", "sph_prime", "sph_build_cells", "sph_sort",
            "sph_density", "sph_forces", "sph_integrate", "sph_step_batched",
            "sph_poll_errors", "sph_set_timing", "sph_stage_times", "sph_stage_name",
-           "sph_stage_count", "sph_substeps", "sph_cell_builds")
+           "sph_stage_count", "sph_substeps", "sph_cell_builds", "sph_set_timing_mask")
 
 SPH_SCHEME_WCSPH, SPH_SCHEME_DUAL = 0, 1
 # parameters of the dual-criteria scheme as published (advection and acoustic
@@ -111,6 +111,7 @@ def lib():
         L.sph_cell_builds.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.sph_poll_errors.argtypes = [vp, C.POINTER(C.c_uint32), vp]
         L.sph_set_timing.argtypes = [vp, C.c_int32]
+        L.sph_set_timing_mask.argtypes = [vp, C.c_uint32]
         L.sph_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32,
                                       C.c_int32, vp]
         L.sph_stage_name.argtypes = [C.c_int32]
@@ -226,6 +227,10 @@ def sph_poll_errors(ctx, stream=None) -> int:
 
 def sph_set_timing(ctx, enable):
     _check(lib().sph_set_timing(ctx, int(bool(enable))))
+
+
+def sph_set_timing_mask(ctx, mask):
+    _check(lib().sph_set_timing_mask(ctx, int(mask)))
 
 
 def sph_stage_count() -> int:
