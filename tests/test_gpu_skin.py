@@ -213,3 +213,33 @@ def test_skin_edge_cases_empty_instance_single_particle_and_clamping():
     assert g0["x"][0, 1] == pytest.approx(0.6 - 0.5 * 9.81 * t * t, abs=1e-12)
     assert h["diag"][1][0] == 0.0 and h["diag"][1][2] == 0.0
     sim.close()
+
+
+@pytest.mark.parametrize("name,list_cap", [("c1_2d", 8), ("tiny_3d", 8), ("c1_2d", -1), ("tiny_3d", -1)])
+def test_skin_stencil_paths_on_reused_cells(name, list_cap):
+    """With a skin, targets whose list overflowed (list_cap = 8: all of them)
+    and plain direct search (list_cap = -1) traverse the cells of the last
+    build, culling stencil rows with the radius 2h + skin: every pair closer
+    than 2h must still be found while the particles have moved less than
+    skin / 2.  Skin 0.01 h, so several builds fall inside the 100 steps."""
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case(name)
+    sim = _sim(case, skin=0.01 * case.h, list_cap=list_cap)
+    refs = oracles_for(case)
+    sim.prime()
+    plan = BuildPlan(0.01 * case.h)
+    for r in refs:
+        r.prime()
+    plan.after_step(refs)
+    for n in range(100):
+        sim.step(1)
+        for r in refs:
+            r.step(1)
+        plan.after_step(refs)
+    _compare(sim, refs, case, 100, 1e-6)
+    assert abs(sim.cell_builds() - plan.builds) <= plan.close_calls and plan.builds > 2
+    flags = sim.poll_errors()
+    assert flags & ~sph.SPH_FLAG_CAPACITY == 0
+    if list_cap > 0:
+        assert flags & sph.SPH_FLAG_CAPACITY
+    sim.close()
