@@ -91,7 +91,14 @@ def candidate_count(sim, h):
             continue
         lo, nc, base = sim.grid(b)
         nx, ny, nz = nc
-        occ_b = occ[base:base + nx * ny * nz].reshape(nz, ny, nx)
+        if getattr(sim, "key_order", "row") == "morton":
+            # tables in tiled Morton order: move them to row-major cells
+            cells = np.arange(nx * ny * nz)
+            cx, cy, cz = cells % nx, (cells // nx) % ny, cells // (nx * ny)
+            mk = morton_key(cx, cy, cz, nc, dim)
+            occ_b = occ[base + mk].reshape(nz, ny, nx)
+        else:
+            occ_b = occ[base:base + nx * ny * nz].reshape(nz, ny, nx)
         # 3^d box sum of occupancy with clamping at the grid edge
         pad = np.pad(occ_b, ((1, 1) if dim == 3 else (0, 0), (1, 1), (1, 1)))
         box = np.zeros_like(occ_b)
@@ -101,8 +108,26 @@ def candidate_count(sim, h):
                     zz = slice(1 + dz, 1 + dz + nz) if dim == 3 else slice(0, nz)
                     box += pad[zz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
         keys = h["key"][f0:f1].astype(np.int64) - base
+        if getattr(sim, "key_order", "row") == "morton":
+            inv = np.empty(int(mk.max()) + 1, dtype=np.int64)
+            inv[mk] = cells
+            keys = inv[keys]
         total += int(box.reshape(-1)[keys].sum()) - (f1 - f0)
     return total
+
+
+def morton_key(cx, cy, cz, nc, dim):
+    """Local key of the tiled Morton order (tiles of 8^d cells, row-major;
+    Morton inside a tile), as the library defines it."""
+    ntx, nty = (nc[0] + 7) // 8, (nc[1] + 7) // 8
+    tile = (cx >> 3) + ntx * ((cy >> 3) + nty * (cz >> 3))
+    m = np.zeros_like(cx)
+    for b in range(3):
+        m |= ((cx >> b) & 1) << (dim * b)
+        m |= ((cy >> b) & 1) << (dim * b + 1)
+        if dim == 3:
+            m |= ((cz >> b) & 1) << (dim * b + 2)
+    return (tile << (3 * dim)) | m
 
 
 def kernel_source_hash():
@@ -171,14 +196,15 @@ def load_valu(workload, precision, kernel):
 
 
 def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
-            list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph", skin_h=0.0):
+            list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph", skin_h=0.0, key_order="row"):
     import torch
     from paper_2603_11868_amd import sph
 
     sim = sph.Simulation(case, precision=precision, reorder_every=reorder_every,
                          use_graph=graph, block_threads=block,
                          list_cap=list_cap, prefetch=prefetch, scheme=scheme,
-                         skin=skin_h * case.h)
+                         skin=skin_h * case.h, key_order=key_order)
+    sim.key_order = key_order
     sim.prime()
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -266,6 +292,8 @@ def main(argv=None):
     ap.add_argument("--reorder-every", type=int, default=None)
     ap.add_argument("--skin", type=float, default=0.1,
                     help="Verlet skin in units of h (0: cells and lists rebuilt every step)")
+    ap.add_argument("--key-order", default="row", choices=("row", "morton"),
+                    help="cell keys: row-major, or tiles of 8^d cells in Morton order")
     ap.add_argument("--no-skin-leg", action="store_true",
                     help="skip the second timing of the headline path without a skin")
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps of the CPU sample (0: skip)")
@@ -305,7 +333,7 @@ def main(argv=None):
                                           reorder_every=args.reorder_every, block=args.block,
                                           list_cap=args.list,
                                           prefetch=args.prefetch, scheme=args.scheme,
-                                          skin_h=args.skin)
+                                          skin_h=args.skin, key_order=args.key_order)
     updates = sim.timed_substeps if args.scheme == "dual" else args.steps
     sim_time = sim.timed_sim_time
     value = n_fluid * updates / secs / 1e6
@@ -385,7 +413,7 @@ def main(argv=None):
                                                    reorder_every=args.reorder_every,
                                                    block=args.block,
                                                    list_cap=args.list, prefetch=args.prefetch,
-                                                   skin_h=args.skin)
+                                                   skin_h=args.skin, key_order=args.key_order)
         v2 = n_fluid * args.steps / secs2 / 1e6
         # difference between the two precisions after the same steps, by particle id
         def by_id(st):
@@ -421,7 +449,8 @@ def main(argv=None):
                                                    stage_steps=min(args.steps, 50),
                                                    reorder_every=args.reorder_every,
                                                    block=args.block, list_cap=args.list,
-                                                   prefetch=args.prefetch, skin_h=0.0)
+                                                   prefetch=args.prefetch, skin_h=0.0,
+                                                   key_order=args.key_order)
         v3 = n_fluid * args.steps / secs3 / 1e6
         no_skin = {"value": round(v3, 3), "ms_per_step": round(secs3 * 1e3 / args.steps, 4),
                    "stage_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages3.items() if n},
@@ -461,7 +490,7 @@ def main(argv=None):
                    "graph": bool(args.graph), "block_threads": args.block or 256,
                    "list_cap": args.list,
                    "prefetch": args.prefetch or 8, "scheme": args.scheme,
-                   "skin_h": args.skin},
+                   "skin_h": args.skin, "key_order": args.key_order},
         "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
         "compare": other, "no_skin": no_skin, "flags": int(flags), **extra,
     }

@@ -69,6 +69,13 @@ typedef enum {
 } sph_scheme;
 
 typedef enum {
+    SPH_KEYS_ROW_MAJOR = 0,  /* cell key cx + ncx (cy + ncy cz) */
+    SPH_KEYS_MORTON_TILES = 1 /* tiles of 8^d cells in row-major order, the
+                                cells of a tile in Morton (Z) order; the key
+                                range is padded to whole tiles */
+} sph_key_order;
+
+typedef enum {
     SPH_FP64 = 0,            /* all arithmetic in FP64 */
     SPH_MIXED = 1            /* FP32 pair sweeps on FP32 offsets from FP64 cell
                                 origins; FP64 state, integration and reductions */
@@ -134,7 +141,8 @@ typedef struct {
                                 use_graph = 0; cfl_ac is then the Courant number
                                 of the acoustic sub-steps (0.6 in the published
                                 scheme), alpha, eps and cfl_f are unused */
-    int32_t reserved0;
+    int32_t key_order;       /* sph_key_order of the cell keys (the order of
+                                the particle sort and of cell_start) */
     double cfl_adv;          /* SPH_SCHEME_DUAL: advection Courant number (0.25) */
     double eta;              /* SPH_SCHEME_DUAL: slope of the Riemann dissipation
                                 limiter (3) */
@@ -191,7 +199,8 @@ const char *sph_last_error(void);
 
 /* Validate and copy the parameters; derive sigma0, the particle mass, the cell
  * grid of every instance (origin tank_lo - 3 dx, ceil((tank extent + 6 dx) /
- * (2h + skin)) cells per axis, x fastest) and the workspace layout.  No device memory is
+ * (2h + skin)) cells per axis; keys row-major, x fastest, or in tiled Morton
+ * order per key_order) and the workspace layout.  No device memory is
  * touched.  On success *out owns a context to be released by sph_destroy. */
 sph_status sph_create(const sph_params *p, sph_ctx **out);
 

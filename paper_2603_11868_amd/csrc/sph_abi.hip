@@ -479,6 +479,8 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     if (pref != 4 && pref != 8) return fail(SPH_E_ARG, "prefetch must be 0, 4 or 8");
     if (lcap > 4096) return fail(SPH_E_ARG, "list_cap must be at most 4096");
     if (p->scheme != SPH_SCHEME_WCSPH && p->scheme != SPH_SCHEME_DUAL) return fail(SPH_E_ARG, "unknown scheme");
+    if (p->key_order != SPH_KEYS_ROW_MAJOR && p->key_order != SPH_KEYS_MORTON_TILES)
+        return fail(SPH_E_ARG, "unknown key order");
     if (p->scheme == SPH_SCHEME_DUAL) {
         if (p->precision != SPH_FP64) return fail(SPH_E_UNSUPPORTED, "the dual scheme runs in FP64 only");
         if (p->use_graph) return fail(SPH_E_UNSUPPORTED, "the dual scheme does not replay graphs");
@@ -508,7 +510,11 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
         InstDev &I = c->idev[b];
         std::memset(&I, 0, sizeof(I));
         instance_grid(d, p->dim, p->dx, cs, I.lo, I.ncell);
-        const int64_t nc = (int64_t)I.ncell[0] * I.ncell[1] * I.ncell[2];
+        // cells of the instance's key range (tiled Morton keys pad the grid to
+        // whole tiles of 8^d cells)
+        const int64_t nc = p->key_order == 0 ? (int64_t)I.ncell[0] * I.ncell[1] * I.ncell[2]
+                                             : (int64_t)((I.ncell[0] + 7) / 8) * ((I.ncell[1] + 7) / 8) *
+                                                   ((I.ncell[2] + 7) / 8) * (p->dim == 3 ? 512 : 64);
         I.cell_base = (int)std::min<int64_t>(C, INT32_MAX);
         I.c0 = d.c0;
         C += nc;
@@ -538,6 +544,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     sc.bcut2 = cs * cs;
     sc.skin = p->skin;
     sc.reorder_every = p->reorder_every;
+    sc.key_order = p->key_order;
     sc.rho0 = p->rho0;
     sc.sigma0 = lattice_number_density(p->dim, p->dx, p->h);
     sc.mass = p->rho0 / sc.sigma0;

@@ -61,7 +61,7 @@ struct SimConst {
     double bcut2;                      // (2h + skin)^2: radius of the cell stencil and the list build
     double skin;                       // Verlet skin (0: cells and lists rebuilt every step)
     int reorder_every;                 // with a skin: reorder at a rebuild this many steps after the last
-    int pad0;
+    int key_order;                     // 0 row-major cells, 1 8^d tiles with Morton order inside
     float fh, finv_h, fcs, fcut2, fkW, fkF, feps_h2, fbcut2;
     float fg[3], pad2;
 };
@@ -73,6 +73,56 @@ template <> struct Rec<2, false> { using v4 = dvec4; using v2 = dvec2; using wpo
 template <> struct Rec<3, false> { using v4 = dvec4; using v2 = dvec2; using wpos_t = dvec4; using real = double; };
 template <> struct Rec<2, true>  { using v4 = fvec4; using v2 = fvec2; using wpos_t = fvec4; using real = float; };
 template <> struct Rec<3, true>  { using v4 = fvec4; using v2 = fvec2; using wpos_t = fvec4; using real = float; };
+
+// ---- cell keys ----------------------------------------------------------------
+//
+// Local key of cell (cx, cy, cz) of an instance.  key_order 0: row-major,
+// x fastest.  key_order 1: the grid is cut into tiles of 8^d cells, taken in
+// row-major order, and the cells of a tile follow the Morton (Z) curve (bits of
+// x, y, z interleaved), so that particles close in space are close in the
+// sorted order in every direction.  Tiles past the grid's edge are padded:
+// their cells stay empty.
+
+__device__ __forceinline__ int spread_bits(int v, int dim)      // 3 bits -> every dim-th bit
+{
+    return dim == 3 ? ((v & 1) | ((v & 2) << 2) | ((v & 4) << 4))
+                    : ((v & 1) | ((v & 2) << 1) | ((v & 4) << 2));
+}
+
+__device__ __forceinline__ int gather_bits(int m, int dim)      // inverse of spread_bits
+{
+    return dim == 3 ? ((m & 1) | ((m >> 2) & 2) | ((m >> 4) & 4))
+                    : ((m & 1) | ((m >> 1) & 2) | ((m >> 2) & 4));
+}
+
+__device__ __forceinline__ int cell_key(const SimConst &sc, const InstDev &I, int cx, int cy, int cz)
+{
+    if (sc.key_order == 0) return cx + I.ncell[0] * (cy + I.ncell[1] * cz);
+    const int ntx = (I.ncell[0] + 7) >> 3, nty = (I.ncell[1] + 7) >> 3;
+    const int tile = (cx >> 3) + ntx * ((cy >> 3) + nty * (cz >> 3));
+    const int m = spread_bits(cx & 7, sc.dim) | (spread_bits(cy & 7, sc.dim) << 1) |
+                  (sc.dim == 3 ? spread_bits(cz & 7, 3) << 2 : 0);
+    return (tile << (3 * sc.dim)) | m;
+}
+
+__device__ __forceinline__ void cell_coords(const SimConst &sc, const InstDev &I, int lk, int &cx, int &cy,
+                                            int &cz)
+{
+    if (sc.key_order == 0) {
+        cx = lk % I.ncell[0];
+        const int t = lk / I.ncell[0];
+        cy = t % I.ncell[1];
+        cz = t / I.ncell[1];
+        return;
+    }
+    const int ntx = (I.ncell[0] + 7) >> 3, nty = (I.ncell[1] + 7) >> 3;
+    const int sh = 3 * sc.dim;
+    const int tile = lk >> sh, m = lk & ((1 << sh) - 1);
+    const int tx = tile % ntx, t2 = tile / ntx;
+    cx = (tx << 3) | gather_bits(m, sc.dim);
+    cy = ((t2 % nty) << 3) | gather_bits(m >> 1, sc.dim);
+    cz = sc.dim == 3 ? (((t2 / nty) << 3) | gather_bits(m >> 2, 3)) : 0;
+}
 
 // ---- wave64 primitives ------------------------------------------------------
 

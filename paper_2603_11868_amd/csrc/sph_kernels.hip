@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_keys(
             int cc[3] = {0, 0, 0};
 #pragma unroll
             for (int c = 0; c < DIM; ++c) cc[c] = cell_1d(xi[c], I.lo[c], sc.inv_cs, I.ncell[c], clamped);
-            k = I.cell_base + cc[0] + I.ncell[0] * (cc[1] + I.ncell[1] * cc[2]);
+            k = I.cell_base + cell_key(sc, I, cc[0], cc[1], cc[2]);
             key[i] = k;
         }
     }

@@ -215,12 +215,11 @@ __device__ __forceinline__ real norm2(const real *r)
 
 // Cell-relative FP32 offsets of a position (the FP64 origin lo + c cs).
 template <int DIM>
-__device__ __forceinline__ void cell_offset_f32(const double *xi, const InstDev &I, int lk, double cs, float *o)
+__device__ __forceinline__ void cell_offset_f32(const SimConst &sc, const double *xi, const InstDev &I, int lk,
+                                                double cs, float *o)
 {
-    const int cx = lk % I.ncell[0];
-    const int t = lk / I.ncell[0];
-    const int cy = t % I.ncell[1];
-    const int cz = t / I.ncell[1];
+    int cx, cy, cz;
+    cell_coords(sc, I, lk, cx, cy, cz);
     o[0] = (float)(xi[0] - (I.lo[0] + cx * cs));
     o[1] = (float)(xi[1] - (I.lo[1] + cy * cs));
     o[2] = DIM == 3 ? (float)(xi[2] - (I.lo[2] + cz * cs)) : 0.0f;
@@ -248,7 +247,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack(
         vi[c] = v[(int64_t)c * n + i];
     }
     float o[3];
-    cell_offset_f32<DIM>(xi, I, lk, sc.cs, o);
+    cell_offset_f32<DIM>(sc, xi, I, lk, sc.cs, o);
     real p[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) p[c] = MIXED ? (real)o[c] : (real)xi[c];
@@ -290,7 +289,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_wall_pack(
 #pragma unroll
     for (int c = 0; c < DIM; ++c) xj[c] = xw[(int64_t)c * nw + j];
     float o[3];
-    cell_offset_f32<DIM>(xj, I, wskey[k] - I.cell_base, sc.cs, o);
+    cell_offset_f32<DIM>(sc, xj, I, wskey[k] - I.cell_base, sc.cs, o);
     typename V::wpos_t w;
     w.x = MIXED ? (real)o[0] : (real)xj[0];
     w.y = MIXED ? (real)o[1] : (real)xj[1];
@@ -351,14 +350,45 @@ struct CellPos {
     int cx, cy, cz;
 };
 
-__device__ __forceinline__ CellPos decode_cell(const InstDev &I, int lk)
+__device__ __forceinline__ CellPos decode_cell(const SimConst &sc, const InstDev &I, int lk)
 {
     CellPos c;
-    c.cx = lk % I.ncell[0];
-    const int t = lk / I.ncell[0];
-    c.cy = t % I.ncell[1];
-    c.cz = t / I.ncell[1];
+    cell_coords(sc, I, lk, c.cx, c.cy, c.cz);
     return c;
+}
+
+// Slot ranges of the cells xlo..xhi of stencil row (yy, zz).  Row-major keys:
+// one range (the row is contiguous), split at cells b1, b2.  Tiled Morton
+// keys: one range per cell.
+struct RowSeg {
+    int s0, s1, b1, b2, x0;
+};
+
+__device__ __forceinline__ int row_segments(const SimConst &sc, int xlo, int xhi)
+{
+    return sc.key_order == 0 ? 1 : xhi - xlo + 1;
+}
+
+__device__ __forceinline__ RowSeg row_segment(const SimConst &sc, const InstDev &I, const int *__restrict__ st,
+                                              int g, int xlo, int xhi, int yy, int zz, bool split)
+{
+    RowSeg r;
+    if (sc.key_order == 0) {
+        const int row = I.cell_base + (yy + I.ncell[1] * zz) * I.ncell[0];
+        r.s0 = st[row + xlo];
+        r.s1 = st[row + xhi + 1];
+        r.b1 = split && xlo + 1 <= xhi ? st[row + xlo + 1] : r.s1;
+        r.b2 = split && xlo + 2 <= xhi ? st[row + xlo + 2] : r.s1;
+        r.x0 = xlo;
+    } else {
+        const int kc = I.cell_base + cell_key(sc, I, xlo + g, yy, zz);
+        r.s0 = st[kc];
+        r.s1 = st[kc + 1];
+        r.b1 = r.s1;
+        r.b2 = r.s1;
+        r.x0 = xlo + g;
+    }
+    return r;
 }
 
 // Offsets of a target inside its own cell, per axis (in [0, cs) up to rounding).
@@ -424,7 +454,7 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
-    const CellPos c = decode_cell(I, lk);
+    const CellPos c = decode_cell(sc, I, lk);
     const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
     const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
@@ -439,16 +469,16 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
             if (yy < 0 || yy >= ncy) continue;
             int xlo, xhi;
             if (!row_cells(o, cs, cut2m, dy, dz, c.cx, ncx, xlo, xhi)) continue;
-            const int row = I.cell_base + (yy + ncy * (c.cz + dz)) * ncx;
+            const int nseg = row_segments(sc, xlo, xhi);
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
                 const int *__restrict__ st = pass == 0 ? cstart : wstart;
-                const int s0 = st[row + xlo], s1 = st[row + xhi + 1];
+              for (int g = 0; g < nseg; ++g) {
                 // cell boundaries inside the row matter only for the FP32 offsets
-                const int b1 = MIXED && xlo + 1 <= xhi ? st[row + xlo + 1] : s1;
-                const int b2 = MIXED && xlo + 2 <= xhi ? st[row + xlo + 2] : s1;
+                const RowSeg sg = row_segment(sc, I, st, g, xlo, xhi, yy, c.cz + dz, MIXED);
+                const int s0 = sg.s0, s1 = sg.s1;
                 RowTarget<DIM, MIXED, real> rt;
-                rt.init(pi, xlo - c.cx, dy, dz, cs, b1, b2);
+                rt.init(pi, sg.x0 - c.cx, dy, dz, cs, sg.b1, sg.b2);
                 for (int s = s0; s < s1; ++s) {
                     if (pass == 0 && s == k) continue;
                     v4 A{};
@@ -467,6 +497,7 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
                         else fn(true, s, r, r2, v4{}, v4{});
                     }
                 }
+              }
             }
         }
     }
@@ -508,7 +539,7 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
     using V = RV<DIM, MIXED>;
     using VF = RV<DIM, true>;
     using real = typename V::real;
-    const CellPos c = decode_cell(I, lk);
+    const CellPos c = decode_cell(sc, I, lk);
     const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
     const real cut2m = cull_margin<MIXED>(sc);
@@ -536,17 +567,16 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
             // same candidates at the same time, one cache line for all of them
             xlo = c.cx > 0 ? c.cx - 1 : c.cx;
             xhi = c.cx < ncx - 1 ? c.cx + 1 : c.cx;
-            const int row = I.cell_base + (yy + ncy * (c.cz + dz)) * ncx;
+            const int nseg = row_segments(sc, xlo, xhi);
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
                 const int *__restrict__ st = pass == 0 ? cstart : wstart;
                 const unsigned wall_bit = pass == 1 ? kWallBit : 0u;
-                const int s0 = st[row + xlo];
-                const int s1 = st[row + xhi + 1];
-                const int b1 = xlo + 1 <= xhi ? st[row + xlo + 1] : s1;
-                const int b2 = xlo + 2 <= xhi ? st[row + xlo + 2] : s1;
+              for (int g = 0; g < nseg; ++g) {
+                const RowSeg sg = row_segment(sc, I, st, g, xlo, xhi, yy, c.cz + dz, true);
+                const int s0 = sg.s0, s1 = sg.s1;
                 RowTarget<DIM, true, float> rf;      // FP32 candidate test
-                rf.init(ci, xlo - c.cx, dy, dz, fcs, b1, b2);
+                rf.init(ci, sg.x0 - c.cx, dy, dz, fcs, sg.b1, sg.b2);
                 for (int t0 = s0; t0 < s1; t0 += U) {
                     float cj[U][3];
 #pragma unroll
@@ -599,6 +629,7 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
                         }
                     }
                 }
+              }
             }
         }
     }

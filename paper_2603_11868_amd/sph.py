@@ -39,6 +39,7 @@ SYMBOLS = ("sph_last_error", "sph_create", "sph_destroy", "sph_get_info", "sph_g
            "sph_stage_count", "sph_substeps", "sph_cell_builds", "sph_set_timing_mask")
 
 SPH_SCHEME_WCSPH, SPH_SCHEME_DUAL = 0, 1
+SPH_KEYS_ROW_MAJOR, SPH_KEYS_MORTON_TILES = 0, 1
 # parameters of the dual-criteria scheme as published (advection and acoustic
 # Courant numbers, dissipation limiter slope)
 DUAL_CFL_ADV, DUAL_CFL_AC, DUAL_ETA = 0.25, 0.6, 3.0
@@ -62,7 +63,7 @@ class sph_params(C.Structure):
                 ("cfl_ac", C.c_double), ("cfl_f", C.c_double), ("g", C.c_double * 3),
                 ("inst", C.POINTER(sph_instance_desc)), ("block_threads", C.c_int32),
                 ("use_graph", C.c_int32), ("list_cap", C.c_int32),
-                ("prefetch", C.c_int32), ("scheme", C.c_int32), ("reserved0", C.c_int32),
+                ("prefetch", C.c_int32), ("scheme", C.c_int32), ("key_order", C.c_int32),
                 ("cfl_adv", C.c_double), ("eta", C.c_double), ("skin", C.c_double),
                 ("reserved", C.c_int32 * 2)]
 
@@ -261,7 +262,7 @@ class Simulation:
     def __init__(self, case, precision="fp64", reorder_every=None, block_threads=0,
                  use_graph=False, device="cuda", alpha=None, g=None,
                  cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0,
-                 scheme="wcsph", skin=0.0):
+                 scheme="wcsph", skin=0.0, key_order="row"):
         import torch
         self.torch = torch
         self.case = case
@@ -296,6 +297,7 @@ class Simulation:
         p.list_cap = int(list_cap)
         p.prefetch = int(prefetch)
         p.skin = float(skin)               # Verlet skin, a length (0: none)
+        p.key_order = {"row": SPH_KEYS_ROW_MAJOR, "morton": SPH_KEYS_MORTON_TILES}[key_order]
         if scheme == "dual":
             p.scheme = SPH_SCHEME_DUAL
             p.cfl_ac = DUAL_CFL_AC if cfl is None else float(cfl)

@@ -108,3 +108,21 @@ class BuildPlan:
         rebuild = not (2.0 * since < lim)
         self.total = 0.0 if rebuild else since
         self.built = rebuild
+
+
+def tiled_morton_key(cx, cy, cz, ncell, dim):
+    """Cell key of the tiled Morton order as documented for SPH_KEYS_MORTON_TILES:
+    tiles of 8^d cells in row-major order, the cells of a tile on the Morton
+    curve (bit b of x, y, z at bit d*b, d*b+1, d*b+2).  Vectorised over numpy
+    integer arrays."""
+    import numpy as np
+    cx, cy, cz = (np.asarray(a, dtype=np.int64) for a in (cx, cy, cz))
+    ntx, nty = (ncell[0] + 7) // 8, (ncell[1] + 7) // 8
+    tile = (cx >> 3) + ntx * ((cy >> 3) + nty * (cz >> 3))
+    m = np.zeros_like(cx)
+    for b in range(3):
+        m |= ((cx >> b) & 1) << (dim * b)
+        m |= ((cy >> b) & 1) << (dim * b + 1)
+        if dim == 3:
+            m |= ((cz >> b) & 1) << (dim * b + 2)
+    return (tile << (3 * dim)) | m

@@ -192,3 +192,19 @@ def test_skin_scales_the_default_list_capacity(sphmod):
     grown = 4 * ((int(-(-96 * 1.25 ** 3 // 1)) + 3) // 4) - 96
     # (less the smaller cell arrays of the coarser grid)
     assert 0.9 * grown * 4 * n <= sizes[1] - sizes[0] <= grown * 4 * n + 4096
+
+
+def test_key_order_option(sphmod):
+    case = dambreak.make_case("tiny_3d")
+    p, descs = _params(sphmod, case, key_order=sphmod.SPH_KEYS_MORTON_TILES)
+    ctx = sphmod.sph_create(p)
+    try:
+        info = sphmod.sph_get_info(ctx)
+        lo, nc, cb = sphmod.sph_get_grid(ctx, 0)
+        tiles = ((nc[0] + 7) // 8) * ((nc[1] + 7) // 8) * ((nc[2] + 7) // 8)
+        assert info.n_cells == tiles * 512
+    finally:
+        sphmod.sph_destroy(ctx)
+    p, descs = _params(sphmod, case, key_order=5)
+    with pytest.raises(sphmod.SphError, match="E_ARG"):
+        sphmod.sph_create(p)
