@@ -5,7 +5,7 @@ plain direct search in both sweeps), the number of candidate records in
 flight per thread of the density sweep, and the reorder period K (how often the
 state arrays are physically re-sorted by cell; the cell table itself is
 rebuilt every step, so K changes results only through summation order), and
-the Verlet skin (in units of h).  A skin pays off through the builds it saves,
+the Verlet skin (in units of h) and the cell key order.  A skin pays off through the builds it saves,
 and how many it saves depends on the flow speed: time it on steps that are
 representative of the run (a window of a few steps from rest saves every
 build and favours large skins).
@@ -30,6 +30,7 @@ LISTS = (0, -1)
 PREFETCHES = (4, 8)
 REORDERS = (1, 5, 20, 50)
 SKINS = (0.0, 0.1)
+KEY_ORDERS = ("row",)
 
 
 def cache_key(arch, dim, precision, n_fluid):
@@ -37,12 +38,14 @@ def cache_key(arch, dim, precision, n_fluid):
     return f"{arch}/d{dim}/{precision}/n2^{bucket}"
 
 
-def time_variant(case, precision, block, list_cap, prefetch, reorder, steps, warmup, skin_h=0.0):
+def time_variant(case, precision, block, list_cap, prefetch, reorder, steps, warmup, skin_h=0.0,
+                 key_order="row"):
     import torch
     from .sph import Simulation
 
     sim = Simulation(case, precision=precision, block_threads=block, list_cap=list_cap,
-                     prefetch=prefetch, reorder_every=reorder, skin=skin_h * case.h)
+                     prefetch=prefetch, reorder_every=reorder, skin=skin_h * case.h,
+                     key_order=key_order)
     try:
         sim.prime()
         sim.step(warmup)
@@ -61,22 +64,23 @@ def time_variant(case, precision, block, list_cap, prefetch, reorder, steps, war
 
 def tune(case, precision="fp64", steps=20, warmup=3, blocks=BLOCKS, lists=LISTS,
          prefetches=PREFETCHES, reorders=REORDERS, cache_path=DEFAULT_CACHE, log=print,
-         skins=SKINS):
+         skins=SKINS, key_orders=KEY_ORDERS):
     """Time every variant; return the fastest as a dict and store it."""
     import torch
 
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     results = []
-    for block, lst, pf, reorder, sk in itertools.product(blocks, lists, prefetches, reorders, skins):
+    for block, lst, pf, reorder, sk, ko in itertools.product(blocks, lists, prefetches, reorders, skins,
+                                                             key_orders):
         if lst < 0 and pf != prefetches[0]:
             continue          # direct search has no list to prefetch for
-        ms, flags = time_variant(case, precision, block, lst, pf, reorder, steps, warmup, sk)
+        ms, flags = time_variant(case, precision, block, lst, pf, reorder, steps, warmup, sk, ko)
         results.append({"block_threads": block, "list_cap": lst, "prefetch": pf,
-                        "reorder_every": reorder, "skin_h": sk, "ms_per_step": round(ms, 5),
-                        "flags": flags})
+                        "reorder_every": reorder, "skin_h": sk, "key_order": ko,
+                        "ms_per_step": round(ms, 5), "flags": flags})
         if log:
-            log(f"  block {block:3d} list {lst:3d} prefetch {pf} K {reorder:3d} skin {sk:4.2f}h: "
-                f"{ms:8.4f} ms/step")
+            log(f"  block {block:3d} list {lst:3d} prefetch {pf} K {reorder:3d} skin {sk:4.2f}h "
+                f"keys {ko}: {ms:8.4f} ms/step")
     ok = [r for r in results if r["flags"] == 0]
     best = min(ok or results, key=lambda r: r["ms_per_step"])
     key = cache_key(arch, case.dim, precision, case.n_fluid)
@@ -118,13 +122,15 @@ def main(argv=None):
     ap.add_argument("--reorders", default=",".join(map(str, REORDERS)))
     ap.add_argument("--lists", default=",".join(map(str, LISTS)))
     ap.add_argument("--skins", default=",".join(map(str, SKINS)), help="Verlet skins in units of h")
+    ap.add_argument("--key-orders", default=",".join(KEY_ORDERS), help="row and/or morton")
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     args = ap.parse_args(argv)
     case = dambreak.make_case(args.case)
     ints = lambda s: tuple(int(v) for v in s.split(","))
     e = tune(case, args.precision, args.steps, args.warmup, ints(args.blocks), ints(args.lists),
              ints(args.prefetches), ints(args.reorders), args.cache,
-             skins=tuple(float(v) for v in args.skins.split(",")))
+             skins=tuple(float(v) for v in args.skins.split(",")),
+             key_orders=tuple(args.key_orders.split(",")))
     print(json.dumps({"case": args.case, "precision": args.precision, "best": e["best"]}))
 
 
