@@ -301,8 +301,6 @@ def main(argv=None):
                     help="also run a plain device copy of this size (PMC calibration)")
     args = ap.parse_args(argv)
 
-    if args.scheme == "dual":
-        args.skin = 0.0                # the dual scheme rebuilds every advection step
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               "here is single-GPU and multi-GPU sharding is not built", file=sys.stderr)
@@ -357,9 +355,9 @@ def main(argv=None):
             roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
-                    "traffic": load_traffic(args.case, "dual", name), "flops_per_launch": float(flops),
-                    "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
-            vi = load_valu(args.case, "dual", name)
+                    "traffic": load_traffic(args.case, "dual" + ("_skin" if args.skin else ""), name),
+                    "flops_per_launch": float(flops), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
+            vi = load_valu(args.case, "dual" + ("_skin" if args.skin else ""), name)
             if vi:
                 per = vi / (avg_s * CLOCK_HZ * N_CU)
                 roof["valu_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
@@ -442,16 +440,17 @@ def main(argv=None):
         torch.cuda.empty_cache()
 
     no_skin = None
-    if args.skin > 0 and not args.no_skin_leg and args.scheme == "wcsph":
+    if args.skin > 0 and not args.no_skin_leg:
         # the same steps with the cell table and lists rebuilt every step
         sim3, h3, secs3, stages3, flags3 = run_gpu(case, args.precision, args.steps, args.warmup,
                                                    args.graph, timing=not args.graph,
                                                    stage_steps=min(args.steps, 50),
                                                    reorder_every=args.reorder_every,
                                                    block=args.block, list_cap=args.list,
-                                                   prefetch=args.prefetch, skin_h=0.0,
-                                                   key_order=args.key_order)
-        v3 = n_fluid * args.steps / secs3 / 1e6
+                                                   prefetch=args.prefetch, scheme=args.scheme,
+                                                   skin_h=0.0, key_order=args.key_order)
+        upd3 = sim3.timed_substeps if args.scheme == "dual" else args.steps
+        v3 = n_fluid * upd3 / secs3 / 1e6
         no_skin = {"value": round(v3, 3), "ms_per_step": round(secs3 * 1e3 / args.steps, 4),
                    "stage_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages3.items() if n},
                    "flags": int(flags3)}

@@ -150,7 +150,7 @@ typedef struct {
                                 2h + skin, lists of the neighbours within
                                 2h + skin, both reused by sph_step_batched
                                 until the particles may have moved skin / 2
-                                (below).  Not with SPH_SCHEME_DUAL */
+                                (below) */
     int32_t reserved[2];
 } sph_params;
 
@@ -292,7 +292,13 @@ sph_status sph_step_batched(sph_ctx *ctx, int32_t n_steps, void *stream);
  * sph_step_batched stays asynchronous and graph replays stay valid.  Between
  * builds key[], perm[], cell_start[] and the neighbour list are those of the
  * last build; count[] is recounted every step.  The stage calls return
- * SPH_E_UNSUPPORTED when a skin is set. */
+ * SPH_E_UNSUPPORTED when a skin is set.
+ * With SPH_SCHEME_DUAL the sub-steps keep the pairs of their advection step,
+ * so the test is exact instead: at the end of an advection step the largest
+ * distance of a particle from its position at the last build, D, is taken
+ * on the device, and the next advection step rebuilds when 2 D reaches
+ * skin (1 - 1e-4).  The workspace then holds x at the last build
+ * (dim*N doubles more). */
 
 /* SPH_SCHEME_DUAL: the acoustic sub-step count of the next advection step of
  * each instance (n[0..B-1]).  Synchronises `stream`. */

@@ -101,7 +101,7 @@ struct sph_ctx {
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
         o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
-        o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax, o_gate, o_disp;
+        o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax, o_gate, o_disp, o_xb;
     // state
     bool bound = false, primed = false, cells_built = false;
     sph_buffers buf{};
@@ -224,6 +224,7 @@ void build_layout(sph_ctx *c)
     // Verlet skin: rebuild / reorder gates, counters and displacement bounds
     c->o_gate = take(sizeof(int) * 8);
     c->o_disp = take(sizeof(double) * 2);
+    c->o_xb = take(c->dual && c->skin ? sizeof(double) * dim * nf : 1);
     c->ws_bytes = off;
 }
 
@@ -341,6 +342,20 @@ bool reorder_due(const sph_ctx *c)
     return c->p.reorder_every > 0 && (c->steps_done % c->p.reorder_every) == 0;
 }
 
+// The prime builds; its reduction (the first scheme) or the displacement
+// check after it (the dual scheme) plans the first step.  The first rebuild
+// after it reorders, as the first step does without a skin.
+hipError_t skin_prime_gates(sph_ctx *c, hipStream_t s)
+{
+    const Dev &d = c->dev;
+    const int K = c->p.reorder_every;
+    hipError_t e = launch_fill_i32(d.gate, 8, 0, s);
+    if (e == hipSuccess) e = launch_fill_i32(d.gate, 1, 1, s);
+    if (e == hipSuccess) e = launch_fill_i32(d.gate + 2, 1, K > 0 ? K - 1 : 0, s);
+    if (e == hipSuccess) e = launch_fill_f64(d.disp, 2, 0.0, s);
+    return e;
+}
+
 // ---- dual-criteria scheme ------------------------------------------------
 
 sph_status do_dual_part(sph_ctx *c, int sub, int part, hipStream_t s, bool timed)
@@ -358,6 +373,7 @@ sph_status dual_reduce(sph_ctx *c, int prime, hipStream_t s, bool timed)
     const Dev &d = c->dev;
     TRY(check_launch(launch_half2(c->sc, d, s, 0), "state partials"));
     TRY(check_launch(launch_fill_i32(d.nsub_max, 1, 0, s), "plan reset"));
+    if (d.gate) TRY(check_launch(launch_skin_displacement(c->sc, d, s), "skin check"));
     return do_reduce(c, prime, s, timed);
 }
 
@@ -367,8 +383,10 @@ sph_status dual_prime(sph_ctx *c, hipStream_t s)
 {
     const Dev &d = c->dev;
     const int64_t B = (int64_t)c->idev.size();
+    if (d.gate) TRY(check_launch(skin_prime_gates(c, s), "fill"));
     TRY(do_keys(c, 0, s, false));
     TRY(do_sort(c, false, s, false));
+    if (d.gate) TRY(check_launch(launch_save_build_positions(c->sc, d, s), "build positions"));
     TRY(do_density(c, 0, s, false));
     TRY(check_launch(launch_fill_f64(d.drho, c->N, 0.0, s), "fill"));
     TRY(check_launch(launch_fill_i32(d.nsub, B, 1, s), "fill"));
@@ -390,6 +408,7 @@ sph_status dual_advection_step(sph_ctx *c, hipStream_t s, bool timed)
     if (nmax < 1 || nmax > (1 << 20)) return fail(SPH_E_STATE, "invalid sub-step plan (non-finite velocities?)");
     TRY(do_keys(c, 0, s, timed));
     TRY(do_sort(c, reorder_due(c), s, timed));
+    if (d.gate) TRY(check_launch(launch_save_build_positions(c->sc, d, s), "build positions"));
     TRY(do_density(c, 0, s, timed));
     TRY(check_launch(launch_fill_f64(d.drho, c->N, 0.0, s), "fill"));
     for (int sub = 0; sub < nmax; ++sub)
@@ -486,7 +505,6 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
         if (p->use_graph) return fail(SPH_E_UNSUPPORTED, "the dual scheme does not replay graphs");
         if (!(p->cfl_adv > 0.0) || !(p->eta >= 0.0))
             return fail(SPH_E_ARG, "the dual scheme needs cfl_adv > 0 and eta >= 0");
-        if (p->skin > 0.0) return fail(SPH_E_UNSUPPORTED, "the dual scheme rebuilds its cells every advection step");
     }
     auto *c = new sph_ctx();
     c->p = *p;
@@ -676,6 +694,7 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.nsub_max = reinterpret_cast<int *>(ws + c->o_nsubmax);
     d.gate = c->skin ? reinterpret_cast<int *>(ws + c->o_gate) : nullptr;
     d.disp = c->skin ? reinterpret_cast<double *>(ws + c->o_disp) : nullptr;
+    d.xb = c->dual && c->skin ? reinterpret_cast<double *>(ws + c->o_xb) : nullptr;
     if (!c->fmap.empty())
         HIP_TRY(hipMemcpyAsync(d.fmap, c->fmap.data(), sizeof(Chunk) * c->fmap.size(), hipMemcpyHostToDevice, s));
     if (!c->wmap.empty())
@@ -712,16 +731,7 @@ sph_status sph_prime(sph_ctx *c, void *stream)
     if (c->dual) {
         TRY(dual_prime(c, s));
     } else {
-        if (c->skin) {
-            // the prime builds; its reduction plans the first step.  The
-            // first rebuild after it reorders (as the first step does
-            // without a skin).
-            const int K = c->p.reorder_every;
-            HIP_TRY(launch_fill_i32(d.gate, 8, 0, s));
-            HIP_TRY(launch_fill_i32(d.gate, 1, 1, s));
-            HIP_TRY(launch_fill_i32(d.gate + 2, 1, K > 0 ? K - 1 : 0, s));
-            HIP_TRY(launch_fill_f64(d.disp, 2, 0.0, s));
-        }
+        if (c->skin) HIP_TRY(skin_prime_gates(c, s));
         TRY(do_keys(c, 0, s, false));
         TRY(do_sort(c, false, s, false));
         TRY(do_density(c, 0, s, false));

@@ -280,6 +280,20 @@ constexpr int kReduceBlock = 1024;     // one block per instance: wide, to keep 
 // bounds since the last build stay below the skin, every pair closer than 2h
 // was closer than 2h + skin at the build, so the cell table and the lists of
 // that build still hold all of them; otherwise the next step rebuilds both.
+// Gates of the next step from its rebuild decision: reorder on a rebuild at
+// least reorder_every steps after the last reorder; count the builds.
+__device__ void skin_gates(const SimConst &sc, int *__restrict__ gate, bool rebuild)
+{
+    const bool built = gate[0] != 0;
+    const bool reordered = gate[1] != 0;
+    const int since = reordered ? 1 : gate[2] + (gate[2] < (1 << 30) ? 1 : 0);
+    gate[0] = rebuild ? 1 : 0;
+    gate[1] = (rebuild && sc.reorder_every > 0 && since >= sc.reorder_every) ? 1 : 0;
+    gate[2] = since;
+    gate[3] = 0;
+    if (built) gate[4] += 1;
+}
+
 __device__ void skin_plan(const SimConst &sc, int *__restrict__ gate, double *__restrict__ disp,
                           double dt_n, double vmax, double amax)
 {
@@ -291,18 +305,72 @@ __device__ void skin_plan(const SimConst &sc, int *__restrict__ gate, double *__
     if (atomicAdd(&gate[3], 1) != sc.n_inst - 1) return;
     __threadfence();
     const double next = __longlong_as_double((long long)atomicExch(bits, 0ull));
-    const bool built = gate[0] != 0;
-    const bool reordered = gate[1] != 0;
-    const double since_build = (built ? 0.0 : disp[0]) + next;
+    const double since_build = (gate[0] != 0 ? 0.0 : disp[0]) + next;
     // margin: far above the rounding of positions and of FP32 pair distances
     const bool rebuild = !(2.0 * since_build < sc.skin * (1.0 - 1e-4));
     disp[0] = rebuild ? 0.0 : since_build;
-    int since = reordered ? 1 : gate[2] + (gate[2] < (1 << 30) ? 1 : 0);
-    gate[0] = rebuild ? 1 : 0;
-    gate[1] = (rebuild && sc.reorder_every > 0 && since >= sc.reorder_every) ? 1 : 0;
-    gate[2] = since;
-    gate[3] = 0;
-    if (built) gate[4] += 1;
+    skin_gates(sc, gate, rebuild);
+}
+
+// Dual scheme with a skin.  The acoustic sub-steps keep the pairs of their
+// advection step, so the list of a build serves an advection step as long as
+// no particle has moved skin / 2 or more since that build (no pair closer
+// than 2h can then have been 2h + skin or further apart).  The test takes the
+// exact displacements at the end of an advection step, which are those at
+// the start of the next; disp[1] holds the largest squared one as ordered bits.
+__global__ __launch_bounds__(256) void k_skin_displacement(SimConst sc, const double *__restrict__ x,
+                                                           const double *__restrict__ xb,
+                                                           int *__restrict__ gate, double *__restrict__ disp)
+{
+    const int64_t n = sc.N;
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double d2 = 0.0;
+        for (int c = 0; c < sc.dim; ++c) {
+            const double e = x[c * n + i] - xb[c * n + i];
+            d2 += e * e;
+        }
+        if (!(d2 <= 1e300)) d2 = 1e300;                       // non-finite position: rebuild
+        m = d2 > m ? d2 : m;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w && red[threadIdx.x + w] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    auto *bits = reinterpret_cast<unsigned long long *>(disp + 1);
+    atomicMax(bits, (unsigned long long)__double_as_longlong(red[0]));
+    __threadfence();
+    if (atomicAdd(&gate[3], 1) != (int)gridDim.x - 1) return;
+    __threadfence();
+    const double D = sqrt(__longlong_as_double((long long)atomicExch(bits, 0ull)));
+    skin_gates(sc, gate, !(2.0 * D < sc.skin * (1.0 - 1e-4)));
+}
+
+// Positions at a build (runs when gate[0] != 0).
+__global__ void k_save_build_positions(double *__restrict__ xb, const double *__restrict__ x, int64_t n,
+                                       const int *__restrict__ gate)
+{
+    if (*gate == 0) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        xb[i] = x[i];
+}
+
+hipError_t launch_skin_displacement(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    k_skin_displacement<<<fill_grid(sc.N), 256, 0, s>>>(sc, d.x, d.xb, d.gate, d.disp);
+    return hipGetLastError();
+}
+
+hipError_t launch_save_build_positions(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    const int64_t n = (int64_t)sc.dim * sc.N;
+    if (n <= 0) return hipSuccess;
+    k_save_build_positions<<<fill_grid(n), 256, 0, s>>>(d.xb, d.x, n, d.gate);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(

@@ -57,6 +57,7 @@ struct Dev {
     // largest bound of the next drift over the instances (as ordered bits)
     int *gate;
     double *disp;
+    double *xb;               // [dim*N] positions at the last build (dual scheme with a skin)
 };
 
 hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s);
@@ -86,6 +87,10 @@ hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kic
 // sub-steps skip it.  list != 0: the sweeps walk the neighbour list of the
 // advection step's summation.
 hipError_t launch_dual_substep(const SimConst &sc, const Dev &d, int sub, int list, hipStream_t s, int part);
+// Dual scheme with a skin: the largest displacement since the last build
+// decides the gates of the next advection step; x is saved at each build.
+hipError_t launch_skin_displacement(const SimConst &sc, const Dev &d, hipStream_t s);
+hipError_t launch_save_build_positions(const SimConst &sc, const Dev &d, hipStream_t s);
 // Per-instance reductions of the partials -> dt, diag, flags.
 hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s);
 

@@ -1359,14 +1359,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     if constexpr (LIST && kCoopWalk) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
-            if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+            if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
             else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         } else {
             for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -1437,12 +1437,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const int lk = skey[kk] - I.cell_base;
     if constexpr (LIST && kCoopWalk) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, false, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (LIST) {
         const int m = lcount[k];
-        if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+        if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
         else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
     } else {
         for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -1456,6 +1456,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
 template <int DIM>
 static void dual_dispatch(const SimConst &sc, const Dev &d, int sub, int list, hipStream_t s, int part)
 {
+    // LIST = 2: lists built with a skin (entries at 2h or beyond skipped)
     using R = Rec<DIM, false>;
     auto *rec = static_cast<typename R::v4 *>(d.rec);
     auto *wpos = static_cast<const typename R::wpos_t *>(d.wpos);
@@ -1465,7 +1466,11 @@ static void dual_dispatch(const SimConst &sc, const Dev &d, int sub, int list, h
                                                          d.nsub, d.dtsub, sub, rec);
         break;
     case 1:
-        if (list)
+        if (list && d.gate)
+            k_dual_pressure<DIM, 2><<<d.nfchunks, d.block, 0, s>>>(
+                sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.a, d.v, d.nsub,
+                d.dtsub, sub, d.partials, d.nlist, d.lcount, d.list_cap);
+        else if (list)
             k_dual_pressure<DIM, 1><<<d.nfchunks, d.block, 0, s>>>(
                 sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.a, d.v, d.nsub,
                 d.dtsub, sub, d.partials, d.nlist, d.lcount, d.list_cap);
@@ -1478,7 +1483,11 @@ static void dual_dispatch(const SimConst &sc, const Dev &d, int sub, int list, h
         k_dual_second<DIM><<<d.nfchunks, d.block, 0, s>>>(sc, d.fmap, d.perm, d.x, d.v, d.nsub, d.dtsub, sub, rec);
         break;
     default:
-        if (list)
+        if (list && d.gate)
+            k_dual_density<DIM, 2><<<d.nfchunks, d.block, 0, s>>>(
+                sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.rho, d.drho, d.nsub,
+                d.dtsub, sub, d.nlist, d.lcount, d.list_cap);
+        else if (list)
             k_dual_density<DIM, 1><<<d.nfchunks, d.block, 0, s>>>(
                 sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, rec, wpos, d.rho, d.drho, d.nsub,
                 d.dtsub, sub, d.nlist, d.lcount, d.list_cap);

@@ -110,6 +110,37 @@ class BuildPlan:
         self.built = rebuild
 
 
+class DualBuildPlan:
+    """The exact rebuild rule of the dual scheme with a skin, applied to the
+    reference's positions: after an advection step, the next one rebuilds
+    when twice the largest distance of a particle from its position at the
+    last build reaches skin (1 - 1e-4).  Start it right after the prime."""
+
+    def __init__(self, skin, refs):
+        import numpy as np
+        self.np = np
+        self.skin = skin
+        self.xb = [r.by_id(r.x).copy() for r in refs]
+        self.builds = 1            # the prime builds
+        self.pending = False
+        self.close_calls = 0
+
+    def after_step(self, refs):
+        np = self.np
+        if self.pending:
+            self.builds += 1
+        x = [r.by_id(r.x) for r in refs]
+        D = max((float(np.sqrt(((xi - xb) ** 2).sum(1)).max()) if len(xi) else 0.0)
+                for xi, xb in zip(x, self.xb))
+        lim = self.skin * (1.0 - 1e-4)
+        # the device's positions differ from these by summation rounding
+        if abs(2.0 * D - lim) <= 1e-6 * lim:
+            self.close_calls += 1
+        self.pending = not (2.0 * D < lim)
+        if self.pending:
+            self.xb = [xi.copy() for xi in x]
+
+
 def tiled_morton_key(cx, cy, cz, ncell, dim):
     """Cell key of the tiled Morton order as documented for SPH_KEYS_MORTON_TILES:
     tiles of 8^d cells in row-major order, the cells of a tile on the Morton

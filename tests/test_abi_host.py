@@ -171,12 +171,28 @@ def test_skin_options_and_grid(sphmod):
     finally:
         sphmod.sph_destroy(ctx)
     for over, status in ((dict(skin=-1e-3), "E_ARG"), (dict(skin=3 * case.h), "E_ARG"),
-                         (dict(skin=float("nan")), "E_ARG"),
-                         (dict(skin=skin, scheme=sphmod.SPH_SCHEME_DUAL, cfl_adv=0.25, eta=3.0),
-                          "UNSUPPORTED")):
+                         (dict(skin=float("nan")), "E_ARG")):
         p, descs = _params(sphmod, case, **over)
         with pytest.raises(sphmod.SphError, match=status):
             sphmod.sph_create(p)
+
+
+def test_dual_scheme_with_a_skin_keeps_positions_of_the_build(sphmod):
+    # the dual scheme tests exact displacements: its workspace also holds x
+    # at the last build (dim * N doubles, 256-byte aligned)
+    case = dambreak.make_case("tiny_3d")
+    dual = dict(scheme=sphmod.SPH_SCHEME_DUAL, cfl_adv=0.25, eta=3.0)
+    sizes = {}
+    for sk, extra in (("wcsph", {}), ("dual", dual)):
+        p, descs = _params(sphmod, case, skin=0.5 * case.h, **extra)
+        ctx = sphmod.sph_create(p)
+        sizes[sk] = sphmod.sph_workspace_size(ctx)
+        sphmod.sph_destroy(ctx)
+    n = case.n_fluid
+    # dual adds Drho (N doubles) and the build positions (dim N doubles) in
+    # place of two 256-byte placeholders
+    extra = sizes["dual"] - sizes["wcsph"]
+    assert 8 * 4 * n - 512 <= extra <= 8 * 4 * n + 512, (extra, n)
 
 
 def test_skin_scales_the_default_list_capacity(sphmod):

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import dambreak
-from _parity import errors, gpu_instance_view, integer_mismatches, oracle_view, oracles_for
+from _parity import DualBuildPlan, errors, gpu_instance_view, integer_mismatches, oracle_view, oracles_for
 
 pytestmark = pytest.mark.gpu
 
@@ -158,3 +158,73 @@ def test_full_size_c2_one_advection_step():
     assert max(e["rho"], e["v"], e["x_beyond_rounding"], e["dt"]) < 1e-9, e
     _check_integers(g, rv, "c2 dual step 1")
     sim.close()
+
+
+@pytest.mark.parametrize("name,skin_h,list_cap", [("c1_2d", 0.3, 0), ("tiny_3d", 0.5, 0),
+                                                   ("small_batch", 0.2, 0), ("tiny_3d", 0.5, -1),
+                                                   ("c1_2d", 0.3, 8)])
+def test_skin_parity_and_build_schedule(name, skin_h, list_cap):
+    """With a skin the sub-step sweeps walk (or, list_cap -1 or overflowed
+    lists, search the cells of) the last build and skip pairs at 2h or
+    beyond, so each advection step sees the pairs closer than 2h at its
+    positions, as the reference does after its rebuild every advection step.
+    Keys, perm and the cell tables are those of the last build (cells of
+    2h + skin) and are not compared; counts are, bit for bit.  The rebuild
+    schedule follows the exact displacement rule on the reference's
+    positions."""
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case(name)
+    sim = _sim(case, skin=skin_h * case.h, list_cap=list_cap)
+    refs = _refs(case)
+    sim.prime()
+    plan = DualBuildPlan(skin_h * case.h, refs)
+    assert sim.cell_builds() == 1
+    for n_done in range(1, 21):
+        sim.step(1)
+        for r in refs:
+            r.dual_step(1)
+        plan.after_step(refs)
+        if n_done in (1, 20):
+            h = sim.host()
+            nsub = sph.sph_substeps(sim.ctx, sim.B)
+            for b, r in enumerate(refs):
+                g = gpu_instance_view(sim, h, b)
+                rv = oracle_view(r)
+                e = errors(g, rv, case.instances[b].fluid)
+                print(name, skin_h, list_cap, b, n_done, e)
+                assert max(e["rho"], e["v"], e["x"]) < 1e-5, e
+                assert max(e["rho"], e["v"], e["x_beyond_rounding"], e["dt"]) < \
+                    (1e-9 if n_done == 1 else 1e-6), (b, n_done, e)
+                assert np.array_equal(g["count"], rv["count"]), (b, n_done)
+                assert nsub[b] == r.dual_plan()[1]
+    builds = sim.cell_builds()
+    print(name, "dual skin builds", builds, "predicted", plan.builds, "of 21")
+    assert abs(builds - plan.builds) <= plan.close_calls
+    assert 1 < plan.builds < 21
+    flags = sim.poll_errors()
+    assert flags & ~sph.SPH_FLAG_CAPACITY == 0
+    assert bool(flags & sph.SPH_FLAG_CAPACITY) == (list_cap > 0)
+    sim.close()
+
+
+def test_skin_matches_no_skin_run():
+    """Dual scheme on the 3D case with and without a skin of 0.5 h: the same
+    pairs in another order, so after 15 advection steps bit-exact counts and
+    summation-rounding differences in the state."""
+    case = dambreak.make_case("tiny_3d")
+    a = _sim(case)
+    b = _sim(case, skin=0.5 * case.h)
+    a.prime()
+    b.prime()
+    a.step(15)
+    b.step(15)
+    ha, hb = a.host(), b.host()
+    oa, ob = np.argsort(ha["id"]), np.argsort(hb["id"])
+    assert np.array_equal(ha["count"][oa], hb["count"][ob])
+    for k in ("x", "v", "rho"):
+        scale = np.abs(ha[k]).max()
+        assert np.abs(ha[k][oa] - hb[k][ob]).max() <= 1e-9 * scale, k
+    assert 1 < b.cell_builds() < 16
+    assert a.poll_errors() == 0 and b.poll_errors() == 0
+    a.close()
+    b.close()
