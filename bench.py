@@ -290,8 +290,9 @@ def main(argv=None):
     ap.add_argument("--list", type=int, default=0, help="neighbour-list capacity (-1: no list)")
     ap.add_argument("--prefetch", type=int, default=0, help="candidate records in flight (4 or 8)")
     ap.add_argument("--reorder-every", type=int, default=None)
-    ap.add_argument("--skin", type=float, default=0.1,
-                    help="Verlet skin in units of h (0: cells and lists rebuilt every step)")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="Verlet skin in units of h (0: cells and lists rebuilt every step; "
+                         "default 0.1, and 0 for the dual scheme)")
     ap.add_argument("--key-order", default="row", choices=("row", "morton"),
                     help="cell keys: row-major, or tiles of 8^d cells in Morton order")
     ap.add_argument("--no-skin-leg", action="store_true",
@@ -301,6 +302,8 @@ def main(argv=None):
                     help="also run a plain device copy of this size (PMC calibration)")
     args = ap.parse_args(argv)
 
+    if args.skin is None:
+        args.skin = 0.0 if args.scheme == "dual" else 0.1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               "here is single-GPU and multi-GPU sharding is not built", file=sys.stderr)
