@@ -100,7 +100,7 @@ struct sph_ctx {
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
-        o_wpos, o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
+        o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
         o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax, o_gate, o_disp, o_xb;
     // state
     bool bound = false, primed = false, cells_built = false;
@@ -200,8 +200,13 @@ void build_layout(sph_ctx *c)
     // the sweep records share their memory with the reorder gather buffer:
     // the reorder runs before the records are packed
     const size_t scr_bytes = nf * sizeof(double) * (2 * dim + 2);
-    c->o_rec = take(std::max(nf * rec_bytes(c->mixed), scr_bytes));
-    c->o_wpos = take((size_t)std::max<int64_t>(c->Nw, 1) * wall_rec_bytes(dim, c->mixed));
+    // the wall records follow the fluid records (and the reorder buffer) in
+    // one region, so that the list walks address both from one base; 64
+    // bytes of padding at its end: a cooperative walk reads whole fluid-record
+    // sizes, also at the last wall record
+    const size_t wrec_off = align256(std::max(nf * rec_bytes(c->mixed), scr_bytes));
+    c->sc.wrec_off = (int64_t)wrec_off;
+    c->o_rec = take(wrec_off + (size_t)std::max<int64_t>(c->Nw, 1) * wall_rec_bytes(dim, c->mixed) + 64);
     c->o_wkey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
     c->o_wskey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
     c->o_partials = take(sizeof(double) * kNPart * std::max<size_t>(c->fmap.size(), 1));
@@ -589,6 +594,12 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     sc.feps_h2 = (float)sc.eps_h2;
     for (int a = 0; a < 3; ++a) sc.fg[a] = (float)p->g[a];
     build_layout(c);
+    // the list walks address fluid and padded wall records with 32-bit byte
+    // offsets from one base
+    if (lcap > 0 && (uint64_t)c->sc.wrec_off + (uint64_t)std::max<int64_t>(Nw, 1) * wall_rec_bytes(p->dim, c->mixed) + 64 >= (1ull << 32)) {
+        delete c;
+        return fail(SPH_E_CAPACITY, "the neighbour-list walks address at most 4 GiB of sweep records; use list_cap = -1");
+    }
     *out = c;
     g_err.clear();
     return SPH_OK;
@@ -670,7 +681,7 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.cnt = reinterpret_cast<int *>(ws + c->o_cnt);
     d.rec = ws + c->o_rec;
     d.scratch = reinterpret_cast<double *>(ws + c->o_rec);
-    d.wpos = ws + c->o_wpos;
+    d.wpos = ws + c->o_rec + c->sc.wrec_off;
     d.cpos = ws + c->o_cpos;
     d.wcpos = ws + c->o_wcpos;
     d.wkey = reinterpret_cast<int *>(ws + c->o_wkey);

@@ -62,6 +62,8 @@ struct SimConst {
     double skin;                       // Verlet skin (0: cells and lists rebuilt every step)
     int reorder_every;                 // with a skin: reorder at a rebuild this many steps after the last
     int key_order;                     // 0 row-major cells, 1 8^d tiles with Morton order inside
+    int64_t wrec_off;                  // bytes from the fluid sweep records to the wall records
+                                       // padded to the same size (list walks; < 2^32 with lists)
     float fh, finv_h, fcs, fcut2, fkW, fkF, feps_h2, fbcut2;
     float fg[3], pad2;
 };

@@ -27,8 +27,11 @@ constexpr bool kSkinSplitWalk = true;
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
 // list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
-constexpr int kCoopRoundsDensity = 4, kCoopRoundsDual = 4;
-template <bool MIXED> constexpr int coop_rounds_force() { return MIXED ? 4 : 2; }
+constexpr int kCoopRoundsDensity = 4, kCoopRoundsForce = 4, kCoopRoundsDual = 4;
+// Their addressing (walk_coop's OWN), as measured on the 2.0 M-particle 3D dam
+// break: owner offsets in the FP64 force sweep (-2 %) and the dual scheme's
+// sub-step sweeps (-3 to -6 %); per-lane addresses in the density sweeps and
+// the mixed force sweep, which the owner offsets slowed by 7 % and 11 %.
 // List entries in flight per lane in the per-lane walks (walk_list: the mixed
 // walk-only density kernel, and every walk when the cooperative gather is
 // off).  Deep prefetch beats occupancy in these L1-bound walks: measured on
@@ -729,9 +732,20 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
 // that lane G g + i needs, so one instruction touches 64 / G lines for whole
 // records.  An LDS exchange (stride G + 1 parts: no bank conflicts) then hands
 // every lane its own record.  All loads of R list positions are issued before
-// any is used; an unneeded part is loaded from a valid address and zeroed.
-// Every lane of the wave must call this, with m = 0 for a lane with nothing to
-// walk.
+// any is used; a position without an entry reads record 0 and is not used.
+// The wall records follow the fluid records in memory (SimConst::wrec_off,
+// the region padded by 64 bytes at its end).  Two ways to address a part:
+//   OWN = false  the group reads each entry (entry + 1, 0 for none) with one
+//                DPP broadcast per lane of the group, and every lane forms
+//                its part's 64-bit address and zeroes the parts that a wall
+//                record or the sweep does not have;
+//   OWN = true   the lane that owns an entry forms one 32-bit byte offset
+//                from the records' base, the group reads it with one DPP
+//                broadcast-and-add per part, and the parts past the end of a
+//                wall record (read from the records after it) are zeroed on
+//                the way out of the LDS: 30-40 % fewer VALU instructions.
+// Every lane of the wave must call this, with m = 0 for a lane with nothing
+// to walk.
 
 // Value of lane G * (lane / G) + I within groups of G = 4 or 2 lanes (DPP
 // quad permutation); 0 from a disabled lane.
@@ -742,11 +756,10 @@ __device__ __forceinline__ unsigned group_bcast(int v)
     return (unsigned)__builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
 }
 
-template <int DIM, bool MIXED, int NEED, bool CHK, int R, class Fn>
+template <int DIM, bool MIXED, int NEED, bool CHK, int R, bool OWN, class Fn>
 __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
                                           const typename RV<DIM, MIXED>::real *pi,
                                           const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
-                                          const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
                                           const uint4 *__restrict__ nlist, int n, Fn &&fn)
 {
     using V = RV<DIM, MIXED>;
@@ -768,10 +781,14 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     const int lane = lane_id();
     const int p = lane & (G - 1);
     const int gb = lane & ~(G - 1);
-    // this lane's part of a record, and of a wall record (part 0 past its end)
+    const char *base = reinterpret_cast<const char *>(rec);
+    const uint32_t woff = (uint32_t)sc.wrec_off;
+    const uint32_t p16 = (uint32_t)p * 16u;
+    // OWN = false: this lane's part of a fluid and of a wall record (a wall
+    // record's part 0 in place of the parts it does not have)
     const bool pNP = p < NP, pNPW = p < NPW;
-    const char *recbp = reinterpret_cast<const char *>(rec) + p * 16;
-    const char *wbp = reinterpret_cast<const char *>(wpos) + (pNPW ? p * 16 : 0);
+    const char *recbp = base + p16;
+    const char *wbp = base + woff + (pNPW ? p16 : 0u);
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
     const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
     int mmax = m;
@@ -787,45 +804,64 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
             bool use[R][G];
 #pragma unroll
             for (int h = 0; h < R; ++h) {
-                // entry + 1, or 0 when there is none (bound_ctrl also gives 0)
-                const int v = q0 + h0 + h < m ? (int)(eq[h0 + h] + 1u) : 0;
-                unsigned vg[G];
-                vg[0] = group_bcast<G, 0>(v);
-                vg[1] = group_bcast<G, 1>(v);
-                if constexpr (G == 4) {
-                    vg[2] = group_bcast<G, 2>(v);
-                    vg[3] = group_bcast<G, 3>(v);
-                }
+                const bool valid = q0 + h0 + h < m;
+                if constexpr (OWN) {
+                    const unsigned e = eq[h0 + h];
+                    const uint32_t sl = e & kSlotMask;
+                    uint32_t off = (e & kWallBit) ? woff + sl * WBYTES : sl * RBYTES;
+                    off = valid ? off : 0u;
+                    uint32_t og[G];
+                    og[0] = group_bcast<G, 0>((int)off);
+                    og[1] = group_bcast<G, 1>((int)off);
+                    if constexpr (G == 4) {
+                        og[2] = group_bcast<G, 2>((int)off);
+                        og[3] = group_bcast<G, 3>((int)off);
+                    }
 #pragma unroll
-                for (int i = 0; i < G; ++i) {
-                    const bool has = vg[i] != 0u;
-                    const unsigned e = vg[i] - 1u;
-                    const uint32_t s = has ? (e & kSlotMask) : 0u;
-                    const bool wall = has && (e & kWallBit) != 0u;
-                    use[h][i] = has && (wall ? pNPW : pNP);
-                    const char *src = wall ? wbp + s * WBYTES : recbp + s * RBYTES;
-                    raw[h][i] = *reinterpret_cast<const part_t *>(src);
+                    for (int i = 0; i < G; ++i) raw[h][i] = *reinterpret_cast<const part_t *>(base + (og[i] + p16));
+                } else {
+                    const int v = valid ? (int)(eq[h0 + h] + 1u) : 0;
+                    unsigned vg[G];
+                    vg[0] = group_bcast<G, 0>(v);
+                    vg[1] = group_bcast<G, 1>(v);
+                    if constexpr (G == 4) {
+                        vg[2] = group_bcast<G, 2>(v);
+                        vg[3] = group_bcast<G, 3>(v);
+                    }
+#pragma unroll
+                    for (int i = 0; i < G; ++i) {
+                        const bool has = vg[i] != 0u;
+                        const unsigned e = vg[i] - 1u;
+                        const uint32_t sl = has ? (e & kSlotMask) : 0u;
+                        const bool wall = has && (e & kWallBit) != 0u;
+                        use[h][i] = has && (wall ? pNPW : pNP);
+                        const char *src = wall ? wbp + sl * WBYTES : recbp + sl * RBYTES;
+                        raw[h][i] = *reinterpret_cast<const part_t *>(src);
+                    }
                 }
             }
 #pragma unroll
             for (int h = 0; h < R; ++h) {
 #pragma unroll
-                for (int i = 0; i < G; ++i) X[(gb + i) * STRIDE + p] = use[h][i] ? raw[h][i] : part_t{};
+                for (int i = 0; i < G; ++i)
+                    X[(gb + i) * STRIDE + p] = OWN || use[h][i] ? raw[h][i] : part_t{};
                 // LDS operations of one wave execute in order: the reads below
                 // see the stores above, and the next stores come after them;
                 // the barriers only keep the compiler from reordering them
                 __builtin_amdgcn_wave_barrier();
                 if (q0 + h0 + h < m) {
                     const unsigned e = eq[h0 + h];
+                    const bool wl = OWN && (e & kWallBit) != 0u;      // parts to zero here
                     const part_t *mine = X + lane * STRIDE;
                     v4 A, B;
                     if constexpr (MIXED) {
                         A = mine[0];
-                        B = NP > 1 ? mine[1] : fvec4{};
+                        B = NP > 1 && !wl ? mine[1] : fvec4{};
                     } else {
-                        const dvec2 p0 = mine[0], p1 = mine[1];
-                        const dvec2 p2 = NP > 2 ? mine[2] : dvec2{0.0, 0.0};
-                        const dvec2 p3 = NP > 3 ? mine[3] : dvec2{0.0, 0.0};
+                        const dvec2 p0 = mine[0];
+                        const dvec2 p1 = NPW > 1 || !wl ? mine[1] : dvec2{0.0, 0.0};
+                        const dvec2 p2 = NP > 2 && !wl ? mine[2] : dvec2{0.0, 0.0};
+                        const dvec2 p3 = NP > 3 && !wl ? mine[3] : dvec2{0.0, 0.0};
                         A.x = p0.x; A.y = p0.y; A.z = p1.x; A.w = p1.y;
                         B.x = p2.x; B.y = p2.y; B.z = p3.x; B.w = p3.y;
                     }
@@ -918,7 +954,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     };
     if constexpr (COOP && LIST == 3) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsDensity, false>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (COOP) {
@@ -943,7 +979,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
                 m = lcount[k];
             }
         }
-        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsDensity, false>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) {
             if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -1105,7 +1141,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, coop_rounds_force<MIXED>()>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, kCoopRoundsForce, !MIXED>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
@@ -1359,7 +1395,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     if constexpr (LIST && kCoopWalk) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual, true>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
@@ -1437,7 +1473,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const int lk = skey[kk] - I.cell_base;
     if constexpr (LIST && kCoopWalk) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, wpos, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual, true>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (LIST) {
