@@ -28,10 +28,6 @@ constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
 // list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
 constexpr int kCoopRoundsDensity = 4, kCoopRoundsForce = 4, kCoopRoundsDual = 4;
-// Their addressing (walk_coop's OWN), as measured on the 2.0 M-particle 3D dam
-// break: owner offsets in the FP64 force sweep (-2 %) and the dual scheme's
-// sub-step sweeps (-3 to -6 %); per-lane addresses in the density sweeps and
-// the mixed force sweep, which the owner offsets slowed by 7 % and 11 %.
 // List entries in flight per lane in the per-lane walks (walk_list: the mixed
 // walk-only density kernel, and every walk when the cooperative gather is
 // off).  Deep prefetch beats occupancy in these L1-bound walks: measured on
@@ -732,20 +728,15 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
 // that lane G g + i needs, so one instruction touches 64 / G lines for whole
 // records.  An LDS exchange (stride G + 1 parts: no bank conflicts) then hands
 // every lane its own record.  All loads of R list positions are issued before
-// any is used; a position without an entry reads record 0 and is not used.
-// The wall records follow the fluid records in memory (SimConst::wrec_off,
-// the region padded by 64 bytes at its end).  Two ways to address a part:
-//   OWN = false  the group reads each entry (entry + 1, 0 for none) with one
-//                DPP broadcast per lane of the group, and every lane forms
-//                its part's 64-bit address and zeroes the parts that a wall
-//                record or the sweep does not have;
-//   OWN = true   the lane that owns an entry forms one 32-bit byte offset
-//                from the records' base, the group reads it with one DPP
-//                broadcast-and-add per part, and the parts past the end of a
-//                wall record (read from the records after it) are zeroed on
-//                the way out of the LDS: 30-40 % fewer VALU instructions.
-// Every lane of the wave must call this, with m = 0 for a lane with nothing
-// to walk.
+// any is used.  The wall records follow the fluid records in memory
+// (SimConst::wrec_off), so that an entry is one 32-bit byte offset from the
+// records' base: the lane that owns the entry forms it, and the group reads
+// it with one DPP broadcast per part, fused with the add of the lane's part
+// offset.  Parts past the end of a (shorter) wall record are read from the
+// records after it (the region ends with 64 bytes of padding) and zeroed on
+// the way out of the LDS; a position without an entry reads record 0 and is
+// not used.  Every lane of the wave must call this, with m = 0 for a lane
+// with nothing to walk.
 
 // Value of lane G * (lane / G) + I within groups of G = 4 or 2 lanes (DPP
 // quad permutation); 0 from a disabled lane.
@@ -756,7 +747,14 @@ __device__ __forceinline__ unsigned group_bcast(int v)
     return (unsigned)__builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
 }
 
-template <int DIM, bool MIXED, int NEED, bool CHK, int R, bool OWN, class Fn>
+// An empty register constraint on a loaded part: the load stays a load into
+// registers where it is written.  A load whose value only goes to an LDS
+// store becomes a global-to-LDS copy placed at the store, after the previous
+// position's pairs, which leaves one position's loads in flight instead of R.
+__device__ __forceinline__ void in_registers(dvec2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+__device__ __forceinline__ void in_registers(fvec4 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w)); }
+
+template <int DIM, bool MIXED, int NEED, bool CHK, int R, class Fn>
 __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
                                           const typename RV<DIM, MIXED>::real *pi,
                                           const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
@@ -784,11 +782,6 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     const char *base = reinterpret_cast<const char *>(rec);
     const uint32_t woff = (uint32_t)sc.wrec_off;
     const uint32_t p16 = (uint32_t)p * 16u;
-    // OWN = false: this lane's part of a fluid and of a wall record (a wall
-    // record's part 0 in place of the parts it does not have)
-    const bool pNP = p < NP, pNPW = p < NPW;
-    const char *recbp = base + p16;
-    const char *wbp = base + woff + (pNPW ? p16 : 0u);
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
     const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
     int mmax = m;
@@ -801,57 +794,37 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
 #pragma unroll
         for (int h0 = 0; h0 < 4; h0 += R) {
             part_t raw[R][G];
-            bool use[R][G];
 #pragma unroll
             for (int h = 0; h < R; ++h) {
                 const bool valid = q0 + h0 + h < m;
-                if constexpr (OWN) {
-                    const unsigned e = eq[h0 + h];
-                    const uint32_t sl = e & kSlotMask;
-                    uint32_t off = (e & kWallBit) ? woff + sl * WBYTES : sl * RBYTES;
-                    off = valid ? off : 0u;
-                    uint32_t og[G];
-                    og[0] = group_bcast<G, 0>((int)off);
-                    og[1] = group_bcast<G, 1>((int)off);
-                    if constexpr (G == 4) {
-                        og[2] = group_bcast<G, 2>((int)off);
-                        og[3] = group_bcast<G, 3>((int)off);
-                    }
-#pragma unroll
-                    for (int i = 0; i < G; ++i) raw[h][i] = *reinterpret_cast<const part_t *>(base + (og[i] + p16));
-                } else {
-                    const int v = valid ? (int)(eq[h0 + h] + 1u) : 0;
-                    unsigned vg[G];
-                    vg[0] = group_bcast<G, 0>(v);
-                    vg[1] = group_bcast<G, 1>(v);
-                    if constexpr (G == 4) {
-                        vg[2] = group_bcast<G, 2>(v);
-                        vg[3] = group_bcast<G, 3>(v);
-                    }
-#pragma unroll
-                    for (int i = 0; i < G; ++i) {
-                        const bool has = vg[i] != 0u;
-                        const unsigned e = vg[i] - 1u;
-                        const uint32_t sl = has ? (e & kSlotMask) : 0u;
-                        const bool wall = has && (e & kWallBit) != 0u;
-                        use[h][i] = has && (wall ? pNPW : pNP);
-                        const char *src = wall ? wbp + sl * WBYTES : recbp + sl * RBYTES;
-                        raw[h][i] = *reinterpret_cast<const part_t *>(src);
-                    }
+                const unsigned e = eq[h0 + h];
+                const uint32_t sl = e & kSlotMask;
+                uint32_t off = (e & kWallBit) ? woff + sl * WBYTES : sl * RBYTES;
+                off = valid ? off : 0u;
+                uint32_t og[G];
+                og[0] = group_bcast<G, 0>((int)off);
+                og[1] = group_bcast<G, 1>((int)off);
+                if constexpr (G == 4) {
+                    og[2] = group_bcast<G, 2>((int)off);
+                    og[3] = group_bcast<G, 3>((int)off);
                 }
+#pragma unroll
+                for (int i = 0; i < G; ++i) raw[h][i] = *reinterpret_cast<const part_t *>(base + (og[i] + p16));
             }
 #pragma unroll
             for (int h = 0; h < R; ++h) {
 #pragma unroll
-                for (int i = 0; i < G; ++i)
-                    X[(gb + i) * STRIDE + p] = OWN || use[h][i] ? raw[h][i] : part_t{};
+                for (int i = 0; i < G; ++i) {
+                    in_registers(raw[h][i]);
+                    X[(gb + i) * STRIDE + p] = raw[h][i];
+                }
                 // LDS operations of one wave execute in order: the reads below
                 // see the stores above, and the next stores come after them;
                 // the barriers only keep the compiler from reordering them
                 __builtin_amdgcn_wave_barrier();
                 if (q0 + h0 + h < m) {
                     const unsigned e = eq[h0 + h];
-                    const bool wl = OWN && (e & kWallBit) != 0u;      // parts to zero here
+                    const bool wl = (e & kWallBit) != 0u;
                     const part_t *mine = X + lane * STRIDE;
                     v4 A, B;
                     if constexpr (MIXED) {
@@ -877,7 +850,7 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
                     }
                     sub_vec<DIM>(t, pj, r);
                     const real r2 = norm2<DIM>(r);
-                    if (!CHK || r2 < cut2) fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, r2, A, B);
+                    if (!CHK || r2 < cut2) fn(wl, (int)(e & kSlotMask), r, r2, A, B);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
@@ -954,7 +927,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     };
     if constexpr (COOP && LIST == 3) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsDensity, false>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (COOP) {
@@ -979,7 +952,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
                 m = lcount[k];
             }
         }
-        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsDensity, false>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) {
             if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -1141,7 +1114,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, kCoopRoundsForce, !MIXED>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, kCoopRoundsForce>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
@@ -1395,7 +1368,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     if constexpr (LIST && kCoopWalk) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual, true>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
@@ -1473,7 +1446,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const int lk = skey[kk] - I.cell_base;
     if constexpr (LIST && kCoopWalk) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual, true>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (LIST) {
