@@ -26,11 +26,17 @@ constexpr bool kSkinSplitWalk = true;
 // List walks gather records cooperatively (walk_coop).
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
-// list positions (rounds) fetched at a time by the cooperative walks (1, 2 or 4)
-constexpr int kCoopRoundsDensity = 4, kCoopRoundsForce = 4, kCoopRoundsDual = 4;
-// List entries in flight per lane in the per-lane walks (walk_list: the mixed
-// walk-only density kernel, and every walk when the cooperative gather is
-// off).  Deep prefetch beats occupancy in these L1-bound walks: measured on
+// List positions fetched at a time by the cooperative walks (1, 2, 4 or 8;
+// eight read two quads of entries per iteration).  Measured on the 2.0 M-particle
+// 3D dam break: eight in the walk-only density kernels (FP64 739 -> 630 us,
+// mixed 500 -> 420 us) and the 3D mixed force (528 -> 417 us); four where
+// eight leave two waves per SIMD (FP64 force 718 -> 782 us with eight), beside
+// the candidate tests (FP64 density build 1512 -> 1660 us with eight) and in
+// the 2D mixed force (64-instance 2D batch: 554 -> 589 us with eight).
+constexpr int kCoopRoundsWalk = 8, kCoopRoundsBuild = 4, kCoopRoundsDual = 4;
+template <int DIM, bool MIXED> constexpr int coop_rounds_force() { return MIXED && DIM == 3 ? 8 : 4; }
+// List entries in flight per lane in the per-lane walks (walk_list: every
+// walk when the cooperative gather is off).  Deep prefetch beats occupancy in these L1-bound walks: measured on
 // the 2.0 M-particle 3D dam break, 16 entries in flight at 2 waves per SIMD
 // (FP64) were faster than 8 at 3 or 4 at 5.
 template <int DIM, bool MIXED> constexpr int skin_walk_u() { return 16; }
@@ -787,12 +793,20 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     int mmax = m;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off, 64));
-    for (int q0 = 0; q0 < mmax; q0 += 4) {
-        uint4 quad = make_uint4(0u, 0u, 0u, 0u);
-        if (q0 < m) quad = nlist[(int64_t)(q0 >> 2) * n + k];
-        const unsigned eq[4] = {quad.x, quad.y, quad.z, quad.w};
+    constexpr int QN = R > 4 ? R / 4 : 1;            // quads of entries per iteration
+    for (int q0 = 0; q0 < mmax; q0 += 4 * QN) {
+        unsigned eq[4 * QN];
 #pragma unroll
-        for (int h0 = 0; h0 < 4; h0 += R) {
+        for (int g = 0; g < QN; ++g) {
+            uint4 quad = make_uint4(0u, 0u, 0u, 0u);
+            if (q0 + 4 * g < m) quad = nlist[(int64_t)((q0 >> 2) + g) * n + k];
+            eq[4 * g] = quad.x;
+            eq[4 * g + 1] = quad.y;
+            eq[4 * g + 2] = quad.z;
+            eq[4 * g + 3] = quad.w;
+        }
+#pragma unroll
+        for (int h0 = 0; h0 < 4 * QN; h0 += R) {
             part_t raw[R][G];
 #pragma unroll
             for (int h = 0; h < R; ++h) {
@@ -891,8 +905,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         if (*gate != 0) return;
     }
     // the cooperative walk needs every lane of the wave, targets or not
-    // (the mixed walk-only kernel is as fast with sixteen entries per lane in flight)
-    constexpr bool COOP = LIST != 0 && use_coop<DIM, MIXED>() && !(MIXED && LIST == 3);
+    constexpr bool COOP = LIST != 0 && use_coop<DIM, MIXED>();
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     const bool act = k < ch.end;
@@ -927,7 +940,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     };
     if constexpr (COOP && LIST == 3) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsWalk>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
         if (!act) return;
     } else if constexpr (COOP) {
@@ -952,7 +965,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
                 m = lcount[k];
             }
         }
-        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsDensity>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsBuild>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap) {
             if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
@@ -1114,7 +1127,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, kCoopRoundsForce>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, coop_rounds_force<DIM, MIXED>()>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
         if (act && m > cap)
             for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
     } else if (act) {
