@@ -26,15 +26,17 @@ constexpr bool kSkinSplitWalk = true;
 // List walks gather records cooperatively (walk_coop).
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
-// List positions fetched at a time by the cooperative walks (1, 2, 4 or 8;
-// eight read two quads of entries per iteration).  Measured on the 2.0 M-particle
-// 3D dam break: eight in the walk-only density kernels (FP64 739 -> 630 us,
-// mixed 500 -> 420 us) and the 3D mixed force (528 -> 417 us); four where
-// eight leave two waves per SIMD (FP64 force 718 -> 782 us with eight), beside
-// the candidate tests (FP64 density build 1512 -> 1660 us with eight) and in
-// the 2D mixed force (64-instance 2D batch: 554 -> 589 us with eight).
+// List positions fetched at a time by the cooperative walks (1, 2, 4, 6 or 8;
+// six and eight read three and two quads of entries per iteration).  Measured
+// on the 2.0 M-particle 3D dam break: eight in the walk-only density kernels
+// (FP64 739 -> 630 us, mixed 500 -> 420 us) and the 3D mixed force
+// (528 -> 417 us); six in the 3D FP64 force (716 -> 673 us; eight leave two
+// waves per SIMD: 782 us); four beside the candidate tests (FP64 density
+// build 1512 -> 1660 us with eight), in the 2D forces (64-instance 2D batch:
+// mixed 554 -> 589 us with eight, FP64 795 -> 916 us with six) and in the
+// dual scheme's sweeps (six: no change; eight: 5 % slower).
 constexpr int kCoopRoundsWalk = 8, kCoopRoundsBuild = 4, kCoopRoundsDual = 4;
-template <int DIM, bool MIXED> constexpr int coop_rounds_force() { return MIXED && DIM == 3 ? 8 : 4; }
+template <int DIM, bool MIXED> constexpr int coop_rounds_force() { return DIM == 3 ? (MIXED ? 8 : 6) : 4; }
 // List entries in flight per lane in the per-lane walks (walk_list: every
 // walk when the cooperative gather is off).  Deep prefetch beats occupancy in these L1-bound walks: measured on
 // the 2.0 M-particle 3D dam break, 16 entries in flight at 2 waves per SIMD
@@ -770,6 +772,7 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     using real = typename V::real;
     using v4 = typename V::v4;
     using part_t = std::conditional_t<MIXED, fvec4, dvec2>;     // 16 bytes
+    static_assert(R == 1 || R == 2 || R == 4 || R == 6 || R == 8, "positions per batch: 1, 2, 4, 6 or 8");
     constexpr int G = MIXED ? 2 : 4;
     // 16-byte parts a sweep needs, of a fluid record and of a wall record
     constexpr int NP = MIXED ? (NEED != NEED_NONE ? 2 : 1)
@@ -793,7 +796,7 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     int mmax = m;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off, 64));
-    constexpr int QN = R > 4 ? R / 4 : 1;            // quads of entries per iteration
+    constexpr int QN = R == 6 ? 3 : (R > 4 ? R / 4 : 1);   // quads of entries per iteration
     for (int q0 = 0; q0 < mmax; q0 += 4 * QN) {
         unsigned eq[4 * QN];
 #pragma unroll
