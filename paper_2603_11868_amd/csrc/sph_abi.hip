@@ -296,7 +296,7 @@ sph_status do_keys(sph_ctx *c, int kick_on, hipStream_t s, bool timed)
     return check_launch(launch_keys(c->sc, c->dev, kick_on, s), "keys");
 }
 
-sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
+sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed, int kick_on = 0)
 {
     const Dev &d = c->dev;
     c->list_valid = false;
@@ -316,7 +316,7 @@ sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
         TRY(check_launch(launch_reorder(c->sc, d, s), "reorder"));
     }
     StageTimer t(c, ST_PACK, s, timed);
-    return check_launch(launch_pack(c->sc, d, c->mixed, s), "pack");
+    return check_launch(launch_pack(c->sc, d, c->mixed, s, kick_on), "pack");
 }
 
 sph_status do_density(sph_ctx *c, int use_dt, hipStream_t s, bool timed)
@@ -425,7 +425,7 @@ sph_status dual_advection_step(sph_ctx *c, hipStream_t s, bool timed)
 sph_status enqueue_step(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
 {
     TRY(do_keys(c, 1, s, timed));
-    TRY(do_sort(c, reorder, s, timed));
+    TRY(do_sort(c, reorder, s, timed, 1));
     TRY(do_density(c, 1, s, timed));
     TRY(do_force(c, 1, s, timed));
     return do_reduce(c, 0, s, timed);

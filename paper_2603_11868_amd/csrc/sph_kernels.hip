@@ -65,14 +65,6 @@ __device__ __forceinline__ int cell_1d(double x, double lo, double inv_cs, int n
     return (int)t;
 }
 
-// Half-step kick and drift, rounded like the plain expressions (no FMA).
-__device__ __forceinline__ void kick_drift(double &x, double &v, double a, double dt)
-{
-#pragma clang fp contract(off)
-    v = v + 0.5 * dt * a;
-    x = x + dt * v;
-}
-
 // cnt[key] += 1 for every valid lane, one atomic per distinct key of the wave.
 __device__ __forceinline__ void aggregated_count(int *cnt, int key, bool valid)
 {
@@ -94,11 +86,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_keys(
     int *__restrict__ cnt, int *__restrict__ clampc, unsigned *__restrict__ flags,
     const int *__restrict__ gate)
 {
+    // a step that reuses its cell table kicks and drifts in k_pack instead
+    if (gate != nullptr && *gate == 0) return;
     const Chunk ch = map[blockIdx.x];
     const int i = ch.begin + threadIdx.x;
     const bool act = i < ch.end;
-    // a step that reuses its cell table only kicks and drifts
-    const bool build = gate == nullptr || *gate != 0;
     int k = 0;
     int clamped = 0;
     if (act) {
@@ -116,15 +108,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_keys(
                 x[(int64_t)c * n + i] = xi[c];
             }
         }
-        if (build) {
-            int cc[3] = {0, 0, 0};
+        int cc[3] = {0, 0, 0};
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) cc[c] = cell_1d(xi[c], I.lo[c], sc.inv_cs, I.ncell[c], clamped);
-            k = I.cell_base + cell_key(sc, I, cc[0], cc[1], cc[2]);
-            key[i] = k;
-        }
+        for (int c = 0; c < DIM; ++c) cc[c] = cell_1d(xi[c], I.lo[c], sc.inv_cs, I.ncell[c], clamped);
+        k = I.cell_base + cell_key(sc, I, cc[0], cc[1], cc[2]);
+        key[i] = k;
     }
-    if (!build) return;
     aggregated_count(cnt, k, act);
     const uint64_t cm = __ballot(act && clamped);
     if (cm && lane_id() == 0) {

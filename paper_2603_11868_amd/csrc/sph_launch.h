@@ -63,7 +63,8 @@ struct Dev {
 hipError_t launch_fill_i32(int *p, int64_t n, int val, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double val, hipStream_t s);
 
-// Keys (optionally after the half-1 kick and drift) and per-cell counts.
+// Keys (optionally after the half-1 kick and drift) and per-cell counts; with
+// a skin only on build steps (gate[0] != 0).
 hipError_t launch_keys(const SimConst &sc, const Dev &d, int kick, hipStream_t s);
 // Wall keys and counts (bind time).
 hipError_t launch_wall_keys(const SimConst &sc, const Dev &d, hipStream_t s);
@@ -71,8 +72,10 @@ hipError_t launch_wall_keys(const SimConst &sc, const Dev &d, hipStream_t s);
 hipError_t launch_wall_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s);
 // Gather x, v, rho, id into sorted order; perm <- identity; key <- sorted keys.
 hipError_t launch_reorder(const SimConst &sc, const Dev &d, hipStream_t s);
-// Sorted sweep records from the storage-order state.
-hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s);
+// Sorted sweep records from the storage-order state.  With a skin, on a step
+// that reuses its cell table (gate[0] == 0) and kick_on != 0, the half-1 kick
+// and drift happen here (launch_keys then returns at once).
+hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s, int kick_on = 0);
 // Density sweep (sph_sweeps.hip).  use_dt = 0 for the prime (dt = 0).  With
 // list_cap > 0 it also writes the per-step neighbour list.
 hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s);

@@ -5,6 +5,15 @@
 
 namespace sphx {
 
+// Half-step kick and drift, rounded like the plain expressions (no FMA).
+__device__ __forceinline__ void kick_drift(double &x, double &v, double a, double dt)
+{
+#pragma clang fp contract(off)
+    v = v + 0.5 * dt * a;
+    x = x + dt * v;
+}
+
+
 // r^2 summed left to right without FMA: the predicate r^2 < (2h)^2 of the FP64
 // path then matches a plain IEEE evaluation bit for bit.
 __device__ __forceinline__ double dist2(double rx, double ry)

@@ -235,9 +235,10 @@ __device__ __forceinline__ void cell_offset_f32(const SimConst &sc, const double
 template <int DIM, bool MIXED>
 __global__ __launch_bounds__(kMaxBlock) void k_pack(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
-    const double *__restrict__ x, const double *__restrict__ v, const int *__restrict__ perm,
+    double *__restrict__ x, double *__restrict__ v, const int *__restrict__ perm,
     const int *__restrict__ skey, int n, typename Rec<DIM, MIXED>::v4 *__restrict__ rec,
-    typename Cand<DIM>::t *__restrict__ cpos, const int *__restrict__ gate)
+    typename Cand<DIM>::t *__restrict__ cpos, const int *__restrict__ gate,
+    const double *__restrict__ a, const double *__restrict__ dt, int kick_on)
 {
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
@@ -252,6 +253,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack(
     for (int c = 0; c < DIM; ++c) {
         xi[c] = x[(int64_t)c * n + i];
         vi[c] = v[(int64_t)c * n + i];
+    }
+    // a step that reuses its cell table (no keys, no sort) kicks and drifts
+    // here, on its way to the records: one pass over the state instead of two
+    if (kick_on && gate != nullptr && *gate == 0) {
+        const double dtb = dt[ch.inst];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            kick_drift(xi[c], vi[c], a[(int64_t)c * n + i], dtb);
+            x[(int64_t)c * n + i] = xi[c];
+            v[(int64_t)c * n + i] = vi[c];
+        }
     }
     float o[3];
     cell_offset_f32<DIM>(sc, xi, I, lk, sc.cs, o);
@@ -318,18 +330,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_wall_pack(
 }
 
 template <int DIM, bool MIXED>
-static void pack_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+static void pack_dispatch(const SimConst &sc, const Dev &d, int kick_on, hipStream_t s)
 {
     k_pack<DIM, MIXED><<<d.nfchunks, d.block, 0, s>>>(
         sc, d.fmap, d.inst, d.x, d.v, d.perm, d.skey, sc.N,
-        static_cast<typename Rec<DIM, MIXED>::v4 *>(d.rec), static_cast<typename Cand<DIM>::t *>(d.cpos), d.gate);
+        static_cast<typename Rec<DIM, MIXED>::v4 *>(d.rec), static_cast<typename Cand<DIM>::t *>(d.cpos), d.gate,
+        d.a, d.dt, kick_on);
 }
 
-hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
+hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t s, int kick_on)
 {
     if (d.nfchunks <= 0) return hipSuccess;
-    if (sc.dim == 2) { if (mixed) pack_dispatch<2, true>(sc, d, s); else pack_dispatch<2, false>(sc, d, s); }
-    else { if (mixed) pack_dispatch<3, true>(sc, d, s); else pack_dispatch<3, false>(sc, d, s); }
+    if (sc.dim == 2) { if (mixed) pack_dispatch<2, true>(sc, d, kick_on, s); else pack_dispatch<2, false>(sc, d, kick_on, s); }
+    else { if (mixed) pack_dispatch<3, true>(sc, d, kick_on, s); else pack_dispatch<3, false>(sc, d, kick_on, s); }
     return hipGetLastError();
 }
 
