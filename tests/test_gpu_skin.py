@@ -78,12 +78,14 @@ def _same_run(case, ha, hb):
     assert max(e.values()) < 1e-6, e
 
 
-def test_skin_mixed_and_graph_match_eager():
+@pytest.mark.parametrize("name,skin_h", [("small_batch", 0.01), ("tiny_3d", 0.02)])
+def test_skin_mixed_and_graph_match_eager(name, skin_h):
     """Mixed precision with a skin, eager and graph-replayed: the same kernels
     in the same order give the same bits, and both follow the reference to
-    the mixed path's gates."""
-    case = dambreak.make_case("small_batch")
-    skin = 0.01 * case.h
+    the mixed path's gates (2D batch, and 3D, whose walks keep eight list
+    positions in flight)."""
+    case = dambreak.make_case(name)
+    skin = skin_h * case.h
     a = _sim(case, precision="mixed", skin=skin)
     b = _sim(case, precision="mixed", skin=skin, use_graph=True)
     refs = oracles_for(case)
@@ -105,8 +107,10 @@ def test_skin_mixed_and_graph_match_eager():
         rv = oracle_view(r)
         e = errors(g, rv, case.instances[bi].fluid)
         assert e["rho"] < 1e-5 and e["v"] < 5e-2, (bi, e)
-        # counts come from FP32 r^2 on the mixed path
-        assert np.count_nonzero(g["count"] != rv["count"]) <= 1e-3 * r.n
+        # counts come from FP32 r^2 on the mixed path: a pair within FP32
+        # rounding of (2h)^2 may fall on either side (at least two allowed,
+        # so that a 600-particle case is not held to none)
+        assert np.count_nonzero(g["count"] != rv["count"]) <= max(2, 1e-3 * r.n)
     assert a.poll_errors() == 0 and b.poll_errors() == 0
     a.close()
     b.close()
