@@ -147,6 +147,88 @@ def test_linear_pressure_field_gradient():
     assert np.abs(r.a[interior, 0]).max() < 1e-9
 
 
+def _lattice_sim(dim, n, dx, v=None):
+    axes = [np.arange(n)] * dim
+    x = (np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, dim) + 0.5) * dx
+    r = O.OracleSim(dim, dx, 1.3 * dx, (0.0,) * dim, (n * dx,) * dim, x, np.zeros((0, dim)), 20.0,
+                    g=(0.0,) * dim, reorder_every=0, v=v)
+    r.keys(); r.sort()
+    r.dual_stage("summation")
+    idx = np.round(x / dx - 0.5).astype(int)
+    interior = np.all((idx >= 3) & (idx < n - 3), axis=1)
+    return r, x, interior
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dual_continuity_of_linear_compression(dim):
+    # v = -beta (x - c) at uniform density and pressure: the velocity jump is
+    # v_i - v* = (v_i - v_j) / 2, so Drho_i = sum_j m (v_i - v_j).grad W_ij,
+    # which is rho0 d beta (div v = -d beta) up to the lattice error
+    n, dx, beta = (24, 0.01, 2.0) if dim == 2 else (12, 0.01, 2.0)
+    axes = [np.arange(n)] * dim
+    x = (np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, dim) + 0.5) * dx
+    r, x, interior = _lattice_sim(dim, n, dx, v=-beta * (x - x.mean(0)))
+    r.rho[:] = 1000.0
+    r.pres[:] = 5000.0
+    r.dual_stage("density", 0.0)
+    ratio = r.drho[interior] / (1000.0 * dim * beta)
+    assert np.all(np.abs(ratio - 1.0) < 0.05), (ratio.min(), ratio.max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dual_continuity_pressure_term(dim):
+    # at rest with p = kappa y^2 and uniform density the velocity jump is the
+    # acoustic term (p_i - p_j) / (Z_i + Z_j) e, so
+    # Drho_i = sum_j (m / rho) (p_i - p_j) F_ij |r_ij| / c0; the odd part of
+    # p_i - p_j = 2 y_i r_y - r_y^2 cancels on the lattice, leaving
+    # -(kappa / c0) int F(r) r r_y^2 dV = -(kappa / c0) (S_d / d) int_0^2h F r^(d+2) dr
+    # (S_2 = 2 pi, S_3 = 4 pi) up to the lattice error.  Positive: the
+    # pressure term diffuses pressure maxima into their neighbourhood.
+    from scipy import integrate
+    n, dx = (24, 0.01) if dim == 2 else (12, 0.01)
+    h, kappa, c0 = 1.3 * dx, 3.0e5, 20.0
+    r, x, interior = _lattice_sim(dim, n, dx)
+    r.rho[:] = 1000.0
+    r.pres[:] = kappa * x[:, dim - 1] ** 2
+    r.dual_stage("density", 0.0)
+    S = 2 * math.pi if dim == 2 else 4 * math.pi
+    moment, _ = integrate.quad(lambda q: O.F(dim, h, q) * q ** (dim + 2), 0.0, 2 * h,
+                               epsabs=0.0, epsrel=1e-12)
+    want = -(kappa / c0) * (S / dim) * moment
+    assert want > 0
+    ratio = r.drho[interior] / want
+    assert np.all(np.abs(ratio - 1.0) < 0.05), (ratio.min(), ratio.max())
+
+
+def test_dual_continuity_pair_with_unequal_states():
+    # one isolated pair with different densities, pressures and velocities:
+    # Drho_1 = 2 rho_1 (m / rho_2) (v_1 - v*).grad_1 W with
+    # v_1 - v* = Z_2 (v_1 - v_2) / (Z_1 + Z_2) + (p_1 - p_2) / (Z_1 + Z_2) e,
+    # Z = rho c0, e = r_12 / |r_12|, evaluated from the numbers
+    dim, dx, c0 = 2, 0.02, 20.0
+    h = 1.3 * dx
+    x = np.array([[0.1, 0.1], [0.1 + 1.1 * h * 0.8, 0.1 - 1.1 * h * 0.6]])
+    v = np.array([[0.3, 0.05], [-0.2, 0.1]])
+    r = O.OracleSim(dim, dx, h, (0.0, 0.0), (0.2, 0.2), x, np.zeros((0, 2)), c0,
+                    g=(0.0, 0.0), reorder_every=0, v=v)
+    r.keys(); r.sort()
+    r.dual_stage("summation")
+    rho = np.array([1000.0, 1200.0])
+    p = np.array([3000.0, 5000.0])
+    r.rho[:] = rho
+    r.pres[:] = p
+    r.dual_stage("density", 0.0)
+    r12 = x[0] - x[1]
+    e = r12 / np.linalg.norm(r12)
+    z1, z2 = rho * c0
+    dv = z2 * (v[0] - v[1]) / (z1 + z2) + (p[0] - p[1]) / (z1 + z2) * e
+    eps = 1e-7 * h
+    grad = np.array([(O.W(2, h, np.linalg.norm(r12 + eps * u)) - O.W(2, h, np.linalg.norm(r12 - eps * u)))
+                     / (2 * eps) for u in np.eye(2)])
+    want = 2.0 * rho[0] * (r.mass / rho[1]) * float(dv @ grad)
+    assert r.drho[0] == pytest.approx(want, rel=1e-6)
+
+
 def test_hydrostatic_column_time_average():
     case = dambreak.make_case("hydrostatic_2d")
     inst = case.instances[0]
@@ -154,14 +236,20 @@ def test_hydrostatic_column_time_average():
     r = O.OracleSim.from_case(case)
     r.dual_prime()
     period = 4 * H / c0
+    ke_early = 0.0
     while r.diag[14] < 6 * period:
         r.dual_step(10)
+        if r.diag[14] < period:
+            ke_early = max(ke_early, r.diag[6])
     bins = np.linspace(0.0, H, 11)
     acc = np.zeros(10)
     nsamp = 0
-    vmax = 0.0
+    vmax = rms_max = ke_late = 0.0
     while r.diag[14] < 10 * period:
         r.dual_step(4)
+        band = (r.x[:, 1] > 0.2 * H) & (r.x[:, 1] < 0.8 * H)
+        rms_max = max(rms_max, math.sqrt((r.v[band] ** 2).sum(1).mean()))
+        ke_late = max(ke_late, r.diag[6])
         y = r.x[:, 1]
         p = np.maximum(0.0, c0 ** 2 * (r.rho - 1000.0))
         which = np.digitize(y, bins) - 1
@@ -176,7 +264,14 @@ def test_hydrostatic_column_time_average():
     band = (mid > 0.2 * H) & (mid < 0.8 * H)
     err = np.abs(mean_p - hydro)[band].max() / (1000.0 * 9.81 * H)
     assert err < 0.05, (err, mean_p, hydro)
-    assert vmax < 0.25 * math.sqrt(9.81 * H)
+    # the uncompressed start rings acoustically at g H / c0 ~ 0.071 sqrt(gH);
+    # the Riemann dissipation acts on compression only, so the ringing is
+    # bounded rather than damped: the bulk stays at that scale and the
+    # kinetic energy does not grow beyond twice that of the first period
+    sq = math.sqrt(9.81 * H)
+    assert rms_max < 0.08 * sq, rms_max / sq
+    assert ke_late < 2.0 * ke_early, (ke_late, ke_early)
+    assert vmax < 0.2 * sq, vmax / sq
 
 
 def test_dam_break_front_below_shallow_water_bound():
