@@ -1,22 +1,23 @@
 """Throughput of the WCSPH step on one MI355X.
 
-Default workload: the 3D dam break of 2.0 M fluid particles (1 x 1 x 2 m block
-at dx = 0.01 in a 4 x 1 x 3 m box, 1.17 M wall particles), plain FP64 path,
-arrays re-sorted by cell every 20 steps, 500 timed steps.  A step is the whole
-hot path: half kick + drift + cell keys, cell scan, radix sort, (reorder),
-sweep records, density sweep, force sweep fused with the second half kick,
-and the FP64 reductions for dt and the diagnostics.  By default the cell
-table and the neighbour lists carry a Verlet skin of 0.1 h: the device
-rebuilds them only when the particles may have moved half the skin (the
-number of builds in the timed steps is reported), and the same steps are
-timed again without a skin.
+Default workload: the large 3D dam break, a 2 x 2 x 2 m fluid block at
+dx = 0.0065 (308^3 = 29,218,112 fluid particles) in an 8 x 2 x 3 m box with
+three layers of wall particles (6,613,248), on the mixed-precision path, the
+arrays re-sorted by cell every 50 steps.  A step is the whole hot path: half
+kick + drift + cell keys, cell scan, radix sort, (reorder), sweep records,
+density sweep (candidate tests and neighbour lists), force sweep fused with
+the second half kick, and the FP64 reductions for dt and the diagnostics.
+The headline rebuilds the cell table and the neighbour lists in every step.
 
 Prints one JSON line.  Besides the headline value it reports the roofline of
 the dominant kernel (algorithmic FLOPs per launch over its HIP-event time in
 the timed steps; only the pair sweeps carry events there, the other stages are
-timed on 50 steps right after),
-the same workload on the mixed-precision path, and the CPU reference timed on
-a bounded sample of the same workload.
+timed on eager steps right after), the conservation drift over the timed
+steps, the same workload on the plain FP64 path together with the error of
+the mixed run against it (density, velocity, position, total energy), the
+headline precision again with a Verlet skin (cells and lists reused between
+builds the device decides on), and the CPU reference timed on a bounded sample
+of the same workload.
 """
 from __future__ import annotations
 
@@ -35,6 +36,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "M particle-updates/s (3D WCSPH step) + achieved HBM GB/s vs FP64 path"
 FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
+FP32_VALU_PEAK_TFLOPS = 157.3    # MI355X FP32 vector, packed (twice the unpacked rate)
 HBM_PEAK_GBS = 8000.0
 SWEEP_STAGES = ("density", "force", "sub_pressure", "sub_density")
 CLOCK_HZ, N_CU = 2.4e9, 256
@@ -157,6 +159,35 @@ def load_traffic(workload, precision, kernel):
     return float(rec["hbm_bytes_per_launch"])
 
 
+def library_source_hash():
+    """Hash of every source of libsph (all kernels of a step)."""
+    hsh = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_11868_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                hsh.update(f.read())
+    return hsh.hexdigest()[:16]
+
+
+def load_step_traffic(workload, precision):
+    """HBM bytes of one whole step (every kernel) from a committed rocprofv3
+    PMC summary taken on the current library sources (else None)."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"step_{workload}_{precision}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^\W*(library_hash|hbm_bytes_per_step)\W*:\s*`?([0-9A-Za-z.+e-]+)", line)
+            if m:
+                rec[m.group(1)] = m.group(2)
+    if rec.get("library_hash") != library_source_hash() or "hbm_bytes_per_step" not in rec:
+        return None
+    return float(rec["hbm_bytes_per_step"])
+
+
 def load_l1(workload, precision, kernel):
     """L1 (TCP) accesses per launch of a sweep from a committed rocprofv3 summary
     taken on the current kernel sources (else None)."""
@@ -197,6 +228,8 @@ def load_valu(workload, precision, kernel):
 
 def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
             list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph", skin_h=0.0, key_order="row"):
+    """One timed leg: prime, `warmup` untimed steps, `steps` timed steps, then
+    optionally `stage_steps` eager steps with events around every stage."""
     import torch
     from paper_2603_11868_amd import sph
 
@@ -210,7 +243,7 @@ def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, b
     torch.cuda.synchronize()
     sub0 = int(sph.sph_get_info(sim.ctx).substeps_done)
     builds0 = sim.cell_builds()
-    tsim0 = sim.host()["diag"][:, 14].copy()
+    diag0 = sim.diag.detach().cpu().numpy().copy()
     if timing:
         # HIP events around the pair sweeps only: events around every stage
         # would slow the timed steps by ~4 %
@@ -223,11 +256,13 @@ def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, b
     sim.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tsim1 = sim.host()["diag"][:, 14].copy()
+    diag1 = sim.diag.detach().cpu().numpy().copy()
     sub1 = int(sph.sph_get_info(sim.ctx).substeps_done)
     sim.timed_builds = sim.cell_builds() - builds0
     sweeps = sph.sph_stage_times(sim.ctx, reset=True) if timing else {}
     sph.sph_set_timing(sim.ctx, 0)
+    # state at the end of the timed steps (before the stage-timing steps)
+    h = sim.host()
     stages = {}
     if stage_steps:
         # every stage, on eager launches of the steps right after the timed
@@ -244,11 +279,89 @@ def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, b
             stages[k] = v
     sim.sweeps_timed = bool(sweeps and any(v[1] for v in sweeps.values()))
     flags = sim.poll_errors()
-    h = sim.host()
     sim.timed_substeps = sub1 - sub0
-    # simulated seconds advanced in the timed region (mean over instances)
-    sim.timed_sim_time = float(np.mean(tsim1 - tsim0))
+    sim.diag0, sim.diag1 = diag0, diag1
     return sim, h, t1 - t0, stages, flags
+
+
+def drift(case, mass, d0, d1):
+    """Conservation over the timed steps from the per-instance diagnostics
+    (slots as in include/sph.h), summed over instances.
+
+    mass_rel: change of the fluid mass (particles are never created or lost,
+    so exactly 0 unless one left the grid); rho_mean: change of mean(rho)/rho0;
+    momentum_residual_rel: impulse of the fluid-fluid forces (zero in exact
+    arithmetic: pairwise forces cancel) over the gravity impulse M |g| t of the
+    same steps; energy: total energy before and after (kinetic + potential +
+    internal; the artificial viscosity dissipates it)."""
+    M0, M1 = d0[:, 2].sum(), d1[:, 2].sum()
+    dt_sum = d1[:, 14] - d0[:, 14]
+    grav = float((d1[:, 2] * case.gmag * dt_sum).sum())
+    res = float((d1[:, 13] - d0[:, 13]).sum())
+    e0 = float((d0[:, 6] + d0[:, 7] + d0[:, 8]).sum())
+    e1 = float((d1[:, 6] + d1[:, 7] + d1[:, 8]).sum())
+    return {
+        "mass_rel": float((M1 - M0) / M0) if M0 else 0.0,
+        "rho_mean_change": float((d1[:, 10] - d0[:, 10]).mean()),
+        "momentum_residual_rel": (res / grav) if grav > 0 else None,
+        "energy_before": e0, "energy_after": e1,
+        "sim_time_s": float(dt_sum.mean()),
+    }
+
+
+def total_energy(case, mass, st):
+    """Kinetic + potential + internal energy of a fluid state (by particle id),
+    internal energy of the clipped equation of state, m c0^2 (ln(rho/rho0) +
+    rho0/rho - 1) for rho > rho0; summed on the host in one fixed order so that
+    two states differ only by their values.  Returns (E, kinetic)."""
+    dim = case.dim
+    off = np.concatenate([[0], np.cumsum([i.n_fluid for i in case.instances])])
+    e_tot, ke_tot = 0.0, 0.0
+    for b, inst in enumerate(case.instances):
+        sl = slice(off[b], off[b + 1])
+        x, v, rho = st["x"][sl], st["v"][sl], st["rho"][sl]
+        ke = 0.5 * mass * np.sum(v * v, axis=1)
+        pe = -mass * (x @ case.g[:dim])
+        ie = np.where(rho > case.rho0,
+                      mass * inst.c0 ** 2 * (np.log(rho / case.rho0) + case.rho0 / rho - 1.0), 0.0)
+        e_tot += float(np.sum(ke + pe + ie))
+        ke_tot += float(np.sum(ke))
+    return e_tot, ke_tot
+
+
+def state_errors(case, mass, test, ref):
+    """Errors of one run against another after the same steps, by particle id,
+    over the probe set (a seeded sample of 10,000 fluid ids plus the corners of
+    the block, per instance) and over all particles:
+    e_rho = max|d rho| / rho0, e_v = max|d v| / max|v_ref|,
+    e_x = max|d x| / max|x_ref - x0| (displacement-normalised), and the total
+    energy error |E - E_ref| / KE_ref (E = kinetic + potential + internal)."""
+    import dambreak
+
+    def by_id(st):
+        out = {}
+        for k in ("x", "v", "rho"):
+            arr = np.empty_like(st[k])
+            arr[st["id"]] = st[k]
+            out[k] = arr
+        return out
+
+    a, b = by_id(test), by_id(ref)
+    x0 = np.concatenate([i.fluid[:, :case.dim] for i in case.instances], 0)
+    off = np.concatenate([[0], np.cumsum([i.n_fluid for i in case.instances])])
+    probe = np.concatenate([off[bb] + dambreak.probe_ids(inst) for bb, inst in enumerate(case.instances)])
+
+    def errs(sel):
+        vref = np.abs(b["v"][sel]).max()
+        disp = np.abs(b["x"][sel] - x0[sel]).max()
+        return {"rho": float(np.abs(a["rho"][sel] - b["rho"][sel]).max() / case.rho0),
+                "v": float(np.abs(a["v"][sel] - b["v"][sel]).max() / max(vref, 1e-300)),
+                "x": float(np.abs(a["x"][sel] - b["x"][sel]).max() / max(disp, 1e-300))}
+
+    e_t, _ = total_energy(case, mass, a)
+    e_r, ke = total_energy(case, mass, b)
+    return {"probe": errs(probe), "all": errs(slice(None)), "n_probe": int(probe.size),
+            "energy_rel_ke": float(abs(e_t - e_r) / ke) if ke > 0 else None}
 
 
 def cpu_baseline(case, nsteps, scheme="wcsph"):
@@ -273,37 +386,95 @@ def cpu_baseline(case, nsteps, scheme="wcsph"):
     return ref, case.n_fluid * nsteps / (t1 - t0) / 1e6, O.num_threads(), t1 - t0
 
 
+def roofline(args, case, sim, h, stages, precision, skin_h):
+    """Roofline of the dominant kernel of a leg: algorithmic FLOPs per launch
+    over its average HIP-event duration, against the vector peak of the
+    precision it computes in."""
+    if not stages:
+        return None
+    name, (ms, n) = max(stages.items(), key=lambda kv: kv[1][0])
+    avg_s = ms / n / 1e3
+    dim = case.dim
+    pairs = float(h["diag"][:, 12].sum())
+    peak = FP64_VALU_PEAK_TFLOPS if precision == "fp64" else FP32_VALU_PEAK_TFLOPS
+    key = precision + ("_skin" if skin_h else "")
+    if name in ("sub_pressure", "sub_density"):
+        # a sub-step sweep walks the pairs of the advection step's list
+        flops = FLOPS_DUAL[dim][name] * pairs
+        achieved = flops / avg_s / 1e12
+        key = "dual" + ("_skin" if skin_h else "")
+        roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
+                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
+                "traffic": load_traffic(args.case, key, name),
+                "flops_per_launch": float(flops), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
+    elif name in ("density", "force"):
+        flops = FLOPS[dim][name] * pairs
+        cands = 0
+        if name == "density":
+            # the candidate tests run in the density sweep of a build step
+            # only (every step without a skin); the force sweep walks the list
+            cands = candidate_count(sim, h)
+            flops += FLOPS[dim]["cand"] * cands * (sim.timed_builds / args.steps)
+        achieved = flops / avg_s / 1e12
+        traffic = load_traffic(args.case, key, name)
+        roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "peak_kind": "FP64 vector" if precision == "fp64" else "FP32 vector (packed)",
+                "traffic": traffic, "flops_per_launch": float(flops),
+                "candidates": int(cands), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
+        if traffic:
+            roof["hbm_gbs"] = round(traffic / avg_s / 1e9, 1)
+    else:
+        return {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None, "avg_ms": round(avg_s * 1e3, 4)}
+    # what bounds the list walks: L1 tag lookups (about one cache access per
+    # clock per CU) and VALU issue (one wave64 instruction per clock per CU,
+    # FP64 and FP32 alike without packed math)
+    acc = load_l1(args.case, key, name)
+    if acc:
+        per = acc / (avg_s * CLOCK_HZ * N_CU)
+        roof["l1"] = {"accesses_per_launch": acc, "per_clock_per_cu": round(per, 3),
+                      "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
+    vi = load_valu(args.case, key, name)
+    if vi:
+        per = vi / (avg_s * CLOCK_HZ * N_CU)
+        roof["valu_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
+                              "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
+    return roof
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--case", default="c2_3d", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--case", default="c5_3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="mixed", choices=("fp64", "mixed"))
     ap.add_argument("--scheme", default="wcsph", choices=("wcsph", "dual"),
                     help="dual: dual-criteria Riemann scheme (steps are advection steps, "
                          "updates are acoustic sub-steps)")
-    ap.add_argument("--compare", default="mixed", choices=("mixed", "fp64", "none"),
-                    help="second precision timed on the same workload")
+    ap.add_argument("--compare", default="fp64", choices=("mixed", "fp64", "none"),
+                    help="second precision timed on the same workload (its state after the "
+                         "run is the reference of the error statement)")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--list", type=int, default=0, help="neighbour-list capacity (-1: no list)")
     ap.add_argument("--prefetch", type=int, default=0, help="candidate records in flight (4 or 8)")
     ap.add_argument("--reorder-every", type=int, default=None)
-    ap.add_argument("--skin", type=float, default=None,
-                    help="Verlet skin in units of h (0: cells and lists rebuilt every step; "
-                         "default 0.1, and 0 for the dual scheme)")
+    ap.add_argument("--skin", type=float, default=0.0,
+                    help="Verlet skin of the headline, in units of h (0: the cell table and "
+                         "the neighbour lists are rebuilt every step)")
+    ap.add_argument("--skin-leg", type=float, default=0.1,
+                    help="also time the headline precision with this skin (units of h; 0: skip)")
     ap.add_argument("--key-order", default="row", choices=("row", "morton"),
                     help="cell keys: row-major, or tiles of 8^d cells in Morton order")
-    ap.add_argument("--no-skin-leg", action="store_true",
-                    help="skip the second timing of the headline path without a skin")
-    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle steps of the CPU sample (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=-1,
+                    help="oracle steps of the CPU sample (0: skip; -1: about 15 s of work)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (PMC calibration)")
     args = ap.parse_args(argv)
 
-    if args.skin is None:
-        args.skin = 0.0 if args.scheme == "dual" else 0.1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               "here is single-GPU and multi-GPU sharding is not built", file=sys.stderr)
@@ -315,10 +486,13 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.scheme == "dual":
+        args.compare = "none"          # the dual scheme runs in FP64 only
+        args.precision = "fp64"
     case = dambreak.make_case(args.case)
     n_fluid = case.n_fluid
     log(f"case {args.case}: {n_fluid} fluid, {case.n_wall} wall; {args.precision}; "
-        f"steps {args.steps} warmup {args.warmup}")
+        f"skin {args.skin} h; steps {args.steps} warmup {args.warmup}")
 
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 8
@@ -328,153 +502,106 @@ def main(argv=None):
         torch.cuda.synchronize()
         del a, b
 
+    common = dict(reorder_every=args.reorder_every, block=args.block, list_cap=args.list,
+                  prefetch=args.prefetch, scheme=args.scheme, key_order=args.key_order,
+                  stage_steps=min(args.steps, 50))
     sim, h, secs, stages, flags = run_gpu(case, args.precision, args.steps, args.warmup,
                                           args.graph, timing=not args.graph,
-                                          stage_steps=min(args.steps, 50),
-                                          reorder_every=args.reorder_every, block=args.block,
-                                          list_cap=args.list,
-                                          prefetch=args.prefetch, scheme=args.scheme,
-                                          skin_h=args.skin, key_order=args.key_order)
+                                          skin_h=args.skin, **common)
     updates = sim.timed_substeps if args.scheme == "dual" else args.steps
-    sim_time = sim.timed_sim_time
     value = n_fluid * updates / secs / 1e6
-    log(f"{args.precision}: {secs * 1e3 / args.steps:.3f} ms/step, {value:.1f} M updates/s, flags {flags}")
+    log(f"{args.precision}: {secs * 1e3 / args.steps:.3f} ms/step, {value:.1f} M updates/s, "
+        f"{sim.timed_builds} builds, flags {flags}")
     for k, (ms, n) in stages.items():
         if n:
             log(f"  {k:12s} {ms / n * 1e3:9.1f} us x {n}")
-
-    # roofline of the dominant kernel
-    roof = None
-    if stages:
-        name, (ms, n) = max(stages.items(), key=lambda kv: kv[1][0])
-        avg_s = ms / n / 1e3
-        dim = case.dim
-        pairs = float(h["diag"][:, 12].sum())
-        cands = candidate_count(sim, h)
-        if name in ("sub_pressure", "sub_density"):
-            # a sub-step sweep walks the pairs of the advection step's list
-            flops = FLOPS_DUAL[dim][name] * pairs
-            achieved = flops / avg_s / 1e12
-            roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
-                    "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
-                    "traffic": load_traffic(args.case, "dual" + ("_skin" if args.skin else ""), name),
-                    "flops_per_launch": float(flops), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
-            vi = load_valu(args.case, "dual" + ("_skin" if args.skin else ""), name)
-            if vi:
-                per = vi / (avg_s * CLOCK_HZ * N_CU)
-                roof["valu_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
-                                      "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
-        elif name in ("density", "force"):
-            # with a skin the candidates are tested at builds only
-            build_frac = sim.timed_builds / args.steps
-            flops = FLOPS[dim]["cand"] * cands * build_frac + FLOPS[dim][name] * pairs
-            achieved = flops / avg_s / 1e12
-            traffic = load_traffic(args.case, args.precision + ("_skin" if args.skin else ""), name)
-            roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
-                    "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
-                    "traffic": traffic, "flops_per_launch": float(flops),
-                    "candidates": int(cands), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
-            if traffic:
-                roof["hbm_gbs"] = round(traffic / avg_s / 1e9, 1)
-            # what bounds the list walks: L1 tag lookups, about one cache
-            # access per clock per CU at most
-            key = args.precision + ("_skin" if args.skin else "")
-            acc = load_l1(args.case, key, name)
-            if acc:
-                per = acc / (avg_s * CLOCK_HZ * N_CU)
-                roof["l1"] = {"accesses_per_launch": acc, "per_clock_per_cu": round(per, 3),
-                              "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
-            # VALU issue: a CU issues at most one wave64 VALU instruction per
-            # clock (4 SIMDs, 4 clocks each); FP64 and FP32 alike here
-            vi = load_valu(args.case, key, name)
-            if vi:
-                per = vi / (avg_s * CLOCK_HZ * N_CU)
-                roof["valu_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
-                                      "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
-        else:
-            roof = {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": None, "traffic": None, "avg_ms": round(avg_s * 1e3, 4)}
+    roof = roofline(args, case, sim, h, stages, args.precision, args.skin)
     stage_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages.items() if n}
-    state_fp = {"x": h["x"], "v": h["v"], "rho": h["rho"], "id": h["id"]}
+    cons = drift(case, sim.info.mass, sim.diag0, sim.diag1)
+    state_head = {"x": h["x"], "v": h["v"], "rho": h["rho"], "id": h["id"]}
+    mass = float(sim.info.mass)
     timed_builds = sim.timed_builds
     sweeps_timed = sim.sweeps_timed
+    sim_time = cons["sim_time_s"]
+    ms_step = secs * 1e3 / args.steps
     sim.close()
-    del sim
+    del sim, h
     torch.cuda.empty_cache()
 
     other = None
-    if args.scheme == "dual":
-        args.compare = "none"          # the dual scheme runs in FP64 only
     if args.compare != "none" and args.compare != args.precision:
         sim2, h2, secs2, stages2, flags2 = run_gpu(case, args.compare, args.steps, args.warmup,
                                                    args.graph, timing=not args.graph,
-                                                   stage_steps=min(args.steps, 50),
-                                                   reorder_every=args.reorder_every,
-                                                   block=args.block,
-                                                   list_cap=args.list, prefetch=args.prefetch,
-                                                   skin_h=args.skin, key_order=args.key_order)
+                                                   skin_h=args.skin, **common)
         v2 = n_fluid * args.steps / secs2 / 1e6
-        # difference between the two precisions after the same steps, by particle id
-        def by_id(st):
-            out = {}
-            for k in ("x", "v", "rho"):
-                arr = np.empty_like(st[k])
-                arr[st["id"]] = st[k]
-                out[k] = arr
-            return out
-        a_, b_ = by_id(state_fp), by_id({"x": h2["x"], "v": h2["v"], "rho": h2["rho"], "id": h2["id"]})
+        # the FP64 run is the reference of the mixed run (either way round)
+        if args.compare == "fp64":
+            err = state_errors(case, mass, state_head, h2)
+        else:
+            err = state_errors(case, mass, h2, state_head)
         other = {
             "precision": args.compare, "value": round(v2, 2),
             "ms_per_step": round(secs2 * 1e3 / args.steps, 4),
-            "ratio_vs_headline": round(v2 / value, 3),
+            "headline_speedup": round(value / v2, 3),
+            "cell_builds": int(sim2.timed_builds),
             "stage_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages2.items() if n},
-            "diff_vs_headline_after_run": {
-                "rho_rel": float(np.abs(a_["rho"] - b_["rho"]).max() / case.rho0),
-                "v_rel": float(np.abs(a_["v"] - b_["v"]).max() / max(np.abs(a_["v"]).max(), 1e-300)),
-                "x_abs_over_dx": float(np.abs(a_["x"] - b_["x"]).max() / case.dx),
-            },
+            "roofline": roofline(args, case, sim2, h2, stages2, args.compare, args.skin),
+            "mixed_vs_fp64_after_run": err,
+            "steps_compared": args.warmup + args.steps,
             "flags": int(flags2),
         }
-        log(f"{args.compare}: {secs2 * 1e3 / args.steps:.3f} ms/step, {v2:.1f} M updates/s")
+        log(f"{args.compare}: {secs2 * 1e3 / args.steps:.3f} ms/step, {v2:.1f} M updates/s; "
+            f"mixed vs fp64: {err['probe']} E {err['energy_rel_ke']}")
         sim2.close()
-        del sim2
+        del sim2, h2
         torch.cuda.empty_cache()
 
-    no_skin = None
-    if args.skin > 0 and not args.no_skin_leg:
-        # the same steps with the cell table and lists rebuilt every step
+    skin_leg = None
+    if args.skin_leg > 0 and args.skin_leg != args.skin:
+        # the same precision with a Verlet skin: cells and lists reused until
+        # the particles may have moved half the skin (builds decided on the device)
         sim3, h3, secs3, stages3, flags3 = run_gpu(case, args.precision, args.steps, args.warmup,
                                                    args.graph, timing=not args.graph,
-                                                   stage_steps=min(args.steps, 50),
-                                                   reorder_every=args.reorder_every,
-                                                   block=args.block, list_cap=args.list,
-                                                   prefetch=args.prefetch, scheme=args.scheme,
-                                                   skin_h=0.0, key_order=args.key_order)
+                                                   skin_h=args.skin_leg, **common)
         upd3 = sim3.timed_substeps if args.scheme == "dual" else args.steps
         v3 = n_fluid * upd3 / secs3 / 1e6
-        no_skin = {"value": round(v3, 3), "ms_per_step": round(secs3 * 1e3 / args.steps, 4),
-                   "stage_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages3.items() if n},
-                   "flags": int(flags3)}
-        log(f"{args.precision} without skin: {secs3 * 1e3 / args.steps:.3f} ms/step, {v3:.1f} M updates/s")
+        skin_leg = {"skin_h": args.skin_leg, "value": round(v3, 3),
+                    "ms_per_step": round(secs3 * 1e3 / args.steps, 4),
+                    "cell_builds": int(sim3.timed_builds),
+                    "stage_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in stages3.items() if n},
+                    "flags": int(flags3)}
+        log(f"{args.precision} with a {args.skin_leg} h skin: {secs3 * 1e3 / args.steps:.3f} ms/step, "
+            f"{v3:.1f} M updates/s, {sim3.timed_builds} builds")
         sim3.close()
-        del sim3
+        del sim3, h3
         torch.cuda.empty_cache()
 
     cpu = None
-    if args.cpu_steps > 0:
-        _, cv, cores, csecs = cpu_baseline(case, args.cpu_steps, args.scheme)
+    cpu_steps = args.cpu_steps
+    if cpu_steps < 0:
+        # about 15 s of oracle work at ~3.5 M updates/s
+        cpu_steps = max(1, int(round(5e7 / max(n_fluid, 1))))
+        cpu_steps = min(cpu_steps, 100)
+    if cpu_steps > 0:
+        _, cv, cores, csecs = cpu_baseline(case, cpu_steps, args.scheme)
         what = "advection steps (their acoustic sub-steps counted)" if args.scheme == "dual" else "full steps"
         cpu = {"value": round(cv, 4), "unit": "M particle-updates/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{args.case}: FP64 CPU reference, prime + {args.cpu_steps} {what} "
-                         f"of all {n_fluid} fluid particles ({csecs:.1f} s)"}
+               "sample": f"{args.case}: FP64 CPU reference, {cpu_steps} {what} after the prime, "
+                         f"all {n_fluid} fluid particles ({csecs:.1f} s timed)"}
         log(f"cpu oracle: {cv:.3f} M updates/s on {cores} threads ({csecs:.1f} s)")
 
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
+    hbm = None
+    step_traffic = load_step_traffic(args.case, args.precision + ("_skin" if args.skin else ""))
+    if step_traffic:
+        hbm = {"bytes_per_step": step_traffic, "achieved_gbs": round(step_traffic / (ms_step / 1e3) / 1e9, 1),
+               "peak_gbs": HBM_PEAK_GBS,
+               "frac": round(step_traffic / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+               "source": "rocprofv3 FETCH_SIZE/WRITE_SIZE of every kernel of a step (profiles/)"}
     extra = {"sim_seconds_per_second": (round(sim_time / secs, 6) if sim_time else None),
              "cell_builds": int(timed_builds),
+             "conservation": cons,
              "stage_timing": ("pair sweeps: HIP events on the library stream in the timed steps; "
                               if sweeps_timed else "") +
                              f"other stages: HIP events on {min(args.steps, 50)} eager steps right after"}
@@ -484,7 +611,7 @@ def main(argv=None):
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "M particle-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(secs * 1e3 / args.steps, 4), "higher_is_better": True,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": WORKLOADS[args.case], "case": args.case,
                    "precision": args.precision, "n_fluid": n_fluid, "n_wall": case.n_wall,
@@ -493,8 +620,8 @@ def main(argv=None):
                    "list_cap": args.list,
                    "prefetch": args.prefetch or 8, "scheme": args.scheme,
                    "skin_h": args.skin, "key_order": args.key_order},
-        "roofline": roof, "cpu_baseline": cpu, "stage_us": stage_us,
-        "compare": other, "no_skin": no_skin, "flags": int(flags), **extra,
+        "roofline": roof, "hbm": hbm, "cpu_baseline": cpu, "stage_us": stage_us,
+        "compare": other, "skin_leg": skin_leg, "flags": int(flags), **extra,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -216,10 +216,10 @@ void build_layout(sph_ctx *c)
     c->o_flags = take(64);
     c->o_clampc = take(sizeof(int) * c->idev.size());
     c->o_lcount = take(sizeof(int) * nf);
-    // FP32 candidate copies (the FP64 path only; the mixed records are FP32)
+    // FP32 cell-offset copies of the positions for the candidate tests
     const size_t cbytes = dim == 3 ? 16 : 8;
-    c->o_cpos = take(c->mixed ? 1 : nf * cbytes);
-    c->o_wcpos = take(c->mixed ? 1 : (size_t)std::max<int64_t>(c->Nw, 1) * cbytes);
+    c->o_cpos = take(nf * cbytes);
+    c->o_wcpos = take((size_t)std::max<int64_t>(c->Nw, 1) * cbytes);
     c->o_nlist = take(c->lcap > 0 ? sizeof(unsigned) * nf * (size_t)c->lcap : 1);
     // dual scheme: continuity rates and the per-instance sub-step plan
     c->o_drho = take(c->dual ? sizeof(double) * nf : 1);
@@ -593,6 +593,17 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     sc.fkF = (float)sc.kF;
     sc.feps_h2 = (float)sc.eps_h2;
     for (int a = 0; a < 3; ++a) sc.fg[a] = (float)p->g[a];
+    // mixed path: lengths in units of cs
+    const double u2 = (2.0 * p->h) / cs;
+    sc.ucut2 = (float)(u2 * u2);
+    sc.ubcut2 = 1.0f;
+    sc.uinv_h = (float)(cs / p->h);
+    sc.ueps_h2 = (float)(p->eps * p->h * p->h / (cs * cs));
+    for (int a = 0; a < 3; ++a) sc.ug[a] = (float)(p->g[a] * cs);
+    sc.uvisc_scale = (float)(p->alpha * p->h / cs);
+    sc.qcut2 = u2 * u2 * 0x1p62;
+    sc.qbcut2 = 0x1p62;
+    sc.qinv_h = cs / p->h * 0x1p-31;
     build_layout(c);
     // the list walks address fluid and padded wall records with 32-bit byte
     // offsets from one base

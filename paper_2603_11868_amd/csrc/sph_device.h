@@ -5,10 +5,10 @@
 //                  component-major SoA; it is physically reordered by cell
 //                  every K steps, so between reorders it stays nearly sorted;
 //   sorted order   per-step sweep records built right after the sort, one
-//                  aligned 64-byte (FP64) or 32-byte (FP32) record per
-//                  particle holding position (FP64, or FP32 offset from the
-//                  FP64 origin of the particle's cell), velocity, and the
-//                  (rho, P) pair written by the density sweep.
+//                  aligned 64-byte (FP64) or 32-byte (mixed) record per
+//                  particle holding position (FP64, or 32-bit fixed-point
+//                  offset from the centre of the particle's cell), velocity,
+//                  and the (rho, P) pair written by the density sweep.
 // Work is split into chunks of at most one block of consecutive particles of
 // one instance, so every block knows its instance and reductions never mix
 // instances.
@@ -66,7 +66,19 @@ struct SimConst {
                                        // padded to the same size (list walks; < 2^32 with lists)
     float fh, finv_h, fcs, fcut2, fkW, fkF, feps_h2, fbcut2;
     float fg[3], pad2;
+    // Mixed path: lengths in units of the cell size cs.  A sweep record holds
+    // the position as 32-bit fixed-point offsets from the centre of the
+    // particle's cell, q = round((x - centre) 2^31 / cs), so that a pair
+    // vector is an exact integer difference (kQUnit below).
+    float ucut2, ubcut2, uinv_h, ueps_h2;   // (2h/cs)^2, ((2h + skin)/cs)^2 = 1, cs/h, eps h^2/cs^2
+    float ug[3], uvisc_scale;                // g cs; alpha h / cs (times c0 per instance)
+    double qcut2, qbcut2, qinv_h;            // the same in fixed-point units (2^-31 cs) for the
+                                             // exact pair tests: (2h/cs)^2 2^62, 2^62, 2^-31 cs/h
 };
+
+// Fixed-point unit of the mixed path's positions: 2^-31 of a cell.
+constexpr float kQUnit = 0x1p-31f;
+constexpr double kQScale = 0x1p31;
 
 // Record types per (dimension, precision): v4 halves of a fluid sweep record,
 // v2 for (rho, P), wpos_t for a wall record.

@@ -79,6 +79,30 @@ __device__ __forceinline__ void kernel_WF(real r2, real inv_h, real kW, real kF,
     F = kF * t3;
 }
 
+// |r| from an FP64 r^2 for the mixed path's density summation: the FP32
+// reciprocal square root refined by one Newton step in FP64 (relative error
+// about 2e-14, far below what the summation needs).
+__device__ __forceinline__ double root_seeded(double r2)
+{
+    const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+    const double g = r2 * y;
+    const double e = fma(-g, 0.5 * y, 0.5);
+    return r2 > 0.0 ? fma(g, e, g) : 0.0;
+}
+
+// Wendland C2 in FP64 from an FP64 r^2 (lengths in any unit: inv_h = 1 / h in
+// that unit), with F rounded to FP32 (mixed path: W enters the summation
+// density, F only the continuity term).
+__device__ __forceinline__ void kernel_WF_exact(double r2, double inv_h, double kW, double kF, double &W, float &F)
+{
+    const double rr = root_seeded(r2);
+    const double q = rr * inv_h;
+    const double t = 1.0 - 0.5 * q;
+    const double t3 = t * t * t;
+    W = kW * t3 * t * (2.0 * q + 1.0);
+    F = (float)(kF * t3);
+}
+
 template <class real>
 __device__ __forceinline__ void kernel_F(real r2, real inv_h, real kF, real &F)
 {

@@ -5,12 +5,22 @@
 // Fluid sweep record, two 4-vectors per particle, rec[2k] = A, rec[2k+1] = B:
 //   3D  A = (x, y, z, vx)   B = (vy, vz, rho, P)
 //   2D  A = (x, y, vx, vy)  B = (rho, P, -, -)
-// x is the FP64 position on the FP64 path and the FP32 offset from the FP64
-// origin of the particle's cell on the mixed path.  k_pack writes A and the
-// velocity half of B; the density sweep writes (rho, P).  One particle's data
-// for the force sweep is one 64-byte (FP64) or 32-byte (FP32) block.
-// Walls: wpos (FP64 position, or FP32 cell offset).  The FP64 path also keeps
-// FP32 cell-offset copies (cpos, wcpos) for cheap candidate tests.
+// x is the FP64 position on the FP64 path.  On the mixed path it is the
+// offset from the centre of the particle's cell as a 32-bit fixed-point
+// number in units of 2^-30 cs (the bits of an int32 in the float slot), and
+// every other component is FP32.  k_pack writes A and the velocity half of
+// B; the density sweep writes (rho, P).  One particle's data for the force
+// sweep is one 64-byte (FP64) or 32-byte (mixed) block.  Walls: wpos (FP64
+// position, or the fixed-point offset).  Both paths keep FP32 offsets from the
+// cell origin, in metres (cpos, wcpos), for cheap candidate tests.
+//
+// Mixed-path geometry.  Pair arithmetic runs in units of the cell size cs.
+// A pair vector is t - q_j 2^-31, t = q_i 2^-31 - (c_j - c_i) in FP32 for
+// the force and the continuity term; the density summation forms the exact
+// integer difference (q_i - (c_j - c_i) 2^31) - q_j in FP64 and evaluates
+// the kernel there: the summation density sets the pressure
+// p = c0^2 (rho - rho0), which magnifies its rounding by rho0 / (rho - rho0),
+// so it needs the FP64 sum of FP64 kernel values, while the force sum does not.
 #include "sph_step_common.h"
 
 #include <type_traits>
@@ -23,6 +33,10 @@ namespace sphx {
 // Skin walks: run the walk of a step without a build in a kernel of its own,
 // free of the candidate-test code and its registers.
 constexpr bool kSkinSplitWalk = true;
+// Candidate tests and list build in a kernel of their own (k_build), the
+// density walk after it: the build then runs at the occupancy of its own
+// registers, not at that of the FP64 density sums.
+constexpr bool kSplitBuild = true;
 // List walks gather records cooperatively (walk_coop).
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
@@ -77,19 +91,41 @@ struct RV {
     using v2 = typename R::v2;
     using wpos_t = typename R::wpos_t;
 
+    // position (mixed: offset from the cell centre in units of cs)
+    __device__ __forceinline__ static real coord(real bits)
+    {
+        if constexpr (MIXED) return (float)__float_as_int(bits) * kQUnit;
+        else return bits;
+    }
     __device__ __forceinline__ static void pos(const v4 &A, real *p)
     {
-        p[0] = A.x;
-        p[1] = A.y;
-        if constexpr (DIM == 3) p[2] = A.z;
+        p[0] = coord(A.x);
+        p[1] = coord(A.y);
+        if constexpr (DIM == 3) p[2] = coord(A.z);
         else p[2] = 0;
     }
     __device__ __forceinline__ static void wall_pos(const wpos_t &w, real *p)
     {
-        p[0] = w.x;
-        p[1] = w.y;
-        if constexpr (DIM == 3) p[2] = w.z;
+        p[0] = coord(w.x);
+        p[1] = coord(w.y);
+        if constexpr (DIM == 3) p[2] = coord(w.z);
         else p[2] = 0;
+    }
+    // a wall record as the A vector of a source (position, zero velocity)
+    __device__ __forceinline__ static v4 wall_A(const wpos_t &w)
+    {
+        v4 A{};
+        A.x = w.x;
+        A.y = w.y;
+        if constexpr (DIM == 3) A.z = w.z;
+        return A;
+    }
+    // fixed-point position (mixed path)
+    __device__ __forceinline__ static void qpos(const v4 &A, int *q)
+    {
+        q[0] = __float_as_int((float)A.x);
+        q[1] = __float_as_int((float)A.y);
+        q[2] = DIM == 3 ? __float_as_int((float)A.z) : 0;
     }
     // velocity from A and the first half of B
     __device__ __forceinline__ static void vel(const v4 &A, const v4 &B, real *v)
@@ -135,6 +171,45 @@ struct RV {
         return B;
     }
 };
+
+// Mixed path: squared distance of a pair from the fixed-point positions, in
+// fixed-point units (2^-31 cs)^2.  qs: the target's offsets plus 2^31, as
+// FP64; Aj: the source's A vector (or wall record); e: a list entry, whose
+// bits 25..30 hold the source cell's offset from the target cell per axis,
+// plus one.  The difference (q_i - (c_j - c_i) 2^31) - q_j is formed in FP64,
+// where every term is an integer below 2^33 and exact, so the result has a
+// single rounding per square and sum, for any pair.
+template <int DIM>
+__device__ __forceinline__ double exact_r2(const double *qs, const fvec4 &Aj, unsigned e)
+{
+    const int qj[3] = {__float_as_int(Aj.x), __float_as_int(Aj.y), DIM == 3 ? __float_as_int(Aj.z) : 0};
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const unsigned o1 = (e >> (25 + 2 * a)) & 3u;       // cell offset + 1
+        const double d = fma((double)o1, -kQScale, qs[a]) - (double)qj[a];
+        r2 = fma(d, d, r2);
+    }
+    return r2;
+}
+
+// The target side of exact_r2.
+template <int DIM>
+__device__ __forceinline__ void exact_target(const int *qi, double *qs)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) qs[a] = a < DIM ? (double)qi[a] + kQScale : 0.0;
+}
+
+// r^2 bound of the walks' pair test.  The FP64 path and the mixed force
+// decide with it; the mixed density sweep (EXACT) widens it by 2e-6 and
+// decides with exact_r2.
+template <bool MIXED, bool EXACT = false>
+__device__ __forceinline__ auto walk_cut2(const SimConst &sc)
+{
+    if constexpr (MIXED) return EXACT ? sc.ucut2 * 1.000002f : sc.ucut2;
+    else return sc.cut2;
+}
 
 // How much of B a sweep needs from each fluid source.
 enum { NEED_NONE = 0, NEED_VEL = 1, NEED_ALL = 2 };
@@ -220,16 +295,27 @@ __device__ __forceinline__ real norm2(const real *r)
 // sweep records
 // ---------------------------------------------------------------------------
 
-// Cell-relative FP32 offsets of a position (the FP64 origin lo + c cs).
+// Fixed-point offset of a coordinate from the centre of its cell, in units of
+// 2^-31 cs, as the bits of an int32 (mixed path).  |q| < 0.75 2^31 for any
+// particle inside the cells of its last build (it has moved less than
+// skin / 2 <= cs / 4 out of them); a particle far outside them (a clamped
+// key) saturates.
+__device__ __forceinline__ float qfix(double off_origin, double cs, double inv_cs)
+{
+    double u = rint((off_origin - 0.5 * cs) * (inv_cs * kQScale));
+    u = fmin(fmax(u, -2147483647.0), 2147483647.0);
+    return __int_as_float((int)u);
+}
+
 template <int DIM>
-__device__ __forceinline__ void cell_offset_f32(const SimConst &sc, const double *xi, const InstDev &I, int lk,
-                                                double cs, float *o)
+__device__ __forceinline__ void cell_offset_f64(const SimConst &sc, const double *xi, const InstDev &I, int lk,
+                                                double *o)
 {
     int cx, cy, cz;
     cell_coords(sc, I, lk, cx, cy, cz);
-    o[0] = (float)(xi[0] - (I.lo[0] + cx * cs));
-    o[1] = (float)(xi[1] - (I.lo[1] + cy * cs));
-    o[2] = DIM == 3 ? (float)(xi[2] - (I.lo[2] + cz * cs)) : 0.0f;
+    o[0] = xi[0] - (I.lo[0] + cx * sc.cs);
+    o[1] = xi[1] - (I.lo[1] + cy * sc.cs);
+    o[2] = DIM == 3 ? xi[2] - (I.lo[2] + cz * sc.cs) : 0.0;
 }
 
 template <int DIM, bool MIXED>
@@ -265,11 +351,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack(
             v[(int64_t)c * n + i] = vi[c];
         }
     }
-    float o[3];
-    cell_offset_f32<DIM>(sc, xi, I, lk, sc.cs, o);
+    double od[3];
+    cell_offset_f64<DIM>(sc, xi, I, lk, od);
     real p[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[c] = MIXED ? (real)o[c] : (real)xi[c];
+    for (int c = 0; c < 3; ++c) {
+        if constexpr (MIXED) p[c] = qfix(od[c], sc.cs, sc.inv_cs);
+        else p[c] = xi[c];
+    }
     typename V::v4 A;
     if constexpr (DIM == 3) {
         A.x = p[0]; A.y = p[1]; A.z = p[2]; A.w = (real)vi[0];
@@ -282,11 +371,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack(
     }
     rec[2 * (int64_t)k] = A;
     // the FP32 copies serve the candidate tests, which only a build runs
-    if (!MIXED && (gate == nullptr || *gate != 0)) {
+    if (gate == nullptr || *gate != 0) {
         typename Cand<DIM>::t cp;
-        cp.x = o[0];
-        cp.y = o[1];
-        if constexpr (DIM == 3) { cp.z = o[2]; cp.w = 0.0f; }
+        cp.x = (float)od[0];
+        cp.y = (float)od[1];
+        if constexpr (DIM == 3) { cp.z = (float)od[2]; cp.w = 0.0f; }
         cpos[k] = cp;
     }
 }
@@ -307,26 +396,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_wall_pack(
     double xj[3] = {0, 0, 0};
 #pragma unroll
     for (int c = 0; c < DIM; ++c) xj[c] = xw[(int64_t)c * nw + j];
-    float o[3];
-    cell_offset_f32<DIM>(sc, xj, I, wskey[k] - I.cell_base, sc.cs, o);
+    double od[3];
+    cell_offset_f64<DIM>(sc, xj, I, wskey[k] - I.cell_base, od);
+    real p[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if constexpr (MIXED) p[c] = qfix(od[c], sc.cs, sc.inv_cs);
+        else p[c] = xj[c];
+    }
     typename V::wpos_t w;
-    w.x = MIXED ? (real)o[0] : (real)xj[0];
-    w.y = MIXED ? (real)o[1] : (real)xj[1];
+    w.x = p[0];
+    w.y = p[1];
     if constexpr (DIM == 3) {
-        w.z = MIXED ? (real)o[2] : (real)xj[2];
+        w.z = p[2];
         w.w = 0;
     } else if constexpr (MIXED) {
         w.z = 0;                           // 16-byte record: zero velocity
         w.w = 0;
     }
     wpos[k] = w;
-    if constexpr (!MIXED) {
-        typename Cand<DIM>::t cp;
-        cp.x = o[0];
-        cp.y = o[1];
-        if constexpr (DIM == 3) { cp.z = o[2]; cp.w = 0.0f; }
-        wcpos[k] = cp;
-    }
+    typename Cand<DIM>::t cp;
+    cp.x = (float)od[0];
+    cp.y = (float)od[1];
+    if constexpr (DIM == 3) { cp.z = (float)od[2]; cp.w = 0.0f; }
+    wcpos[k] = cp;
 }
 
 template <int DIM, bool MIXED>
@@ -418,9 +511,10 @@ __device__ __forceinline__ void target_offsets(const SimConst &sc, const InstDev
                                                typename RV<DIM, MIXED>::real *o)
 {
     if constexpr (MIXED) {
-        o[0] = pi[0];
-        o[1] = pi[1];
-        o[2] = pi[2];
+        // pi: offsets from the cell centre in units of cs
+        o[0] = pi[0] + 0.5f;
+        o[1] = pi[1] + 0.5f;
+        o[2] = DIM == 3 ? pi[2] + 0.5f : 0.0f;
     } else {
         o[0] = pi[0] - (I.lo[0] + c.cx * sc.cs);
         o[1] = pi[1] - (I.lo[1] + c.cy * sc.cs);
@@ -454,13 +548,15 @@ __device__ __forceinline__ bool row_cells(const real *o, real cs, real cut2m, in
 template <bool MIXED>
 __device__ __forceinline__ auto cull_margin(const SimConst &sc)
 {
-    if constexpr (MIXED) return sc.fbcut2 * (float)(1.0 + 1e-5);
+    if constexpr (MIXED) return sc.ubcut2 * (float)(1.0 + 1e-5);     // units of cs
     else return sc.bcut2 * (1.0 + 1e-9);
 }
 
 // ---------------------------------------------------------------------------
-// direct search: fn(wall, s, r, r2, A_j, B_j) for every neighbour of target k,
-// fluid slots of a stencil row first, then its wall slots; rows in z, y order
+// direct search: fn(wall, s, r, r2, A_j, B_j, e) for every neighbour of target
+// k (r^2 < cut2), fluid slots of a stencil row first, then its wall slots;
+// rows in z, y order.  e carries the source's list-entry bits (wall flag, slot
+// and the source cell's offset from the target cell).
 // ---------------------------------------------------------------------------
 
 template <int DIM, bool MIXED, int NEED, class Fn>
@@ -469,15 +565,14 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
                                                const int *__restrict__ cstart, const int *__restrict__ wstart,
                                                const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
                                                const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
-                                               Fn &&fn)
+                                               typename RV<DIM, MIXED>::real cut2, Fn &&fn)
 {
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
     const CellPos c = decode_cell(sc, I, lk);
     const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
-    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
-    const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
+    const real cs = MIXED ? (real)1 : (real)sc.cs;
     const real cut2m = cull_margin<MIXED>(sc);
     real o[3];
     target_offsets<DIM, MIXED>(sc, I, c, pi, o);
@@ -501,20 +596,16 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
                 rt.init(pi, sg.x0 - c.cx, dy, dz, cs, sg.b1, sg.b2);
                 for (int s = s0; s < s1; ++s) {
                     if (pass == 0 && s == k) continue;
-                    v4 A{};
+                    const v4 A = pass == 0 ? V::loadA(rec, s) : V::wall_A(wpos[s]);
                     real pj[3], t[3], r[3];
-                    if (pass == 0) {
-                        A = V::loadA(rec, s);
-                        V::pos(A, pj);
-                    } else {
-                        V::wall_pos(wpos[s], pj);
-                    }
+                    V::pos(A, pj);
                     rt.at(s, t);
                     sub_vec<DIM>(t, pj, r);
                     const real r2 = norm2<DIM>(r);
                     if (r2 < cut2) {
-                        if (pass == 0) fn(false, s, r, r2, A, load_need<DIM, MIXED, NEED>(rec, s));
-                        else fn(true, s, r, r2, v4{}, v4{});
+                        const unsigned e = (pass == 0 ? 0u : kWallBit) | (unsigned)s | rt.bits(s);
+                        if (pass == 0) fn(false, s, r, r2, A, load_need<DIM, MIXED, NEED>(rec, s), e);
+                        else fn(true, s, r, r2, A, v4{}, e);
                     }
                 }
               }
@@ -537,18 +628,20 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
 // Phase 1: candidate tests of target k, hits appended to its list.  Returns the
 // number of hits (possibly above cap; only the first cap are stored).
 //
-// Candidates are read as FP32 cell offsets (the A vectors on the mixed path,
-// the cpos copies on the FP64 path), U per lane in flight, with the index
-// clamped instead of branched.  The mixed path decides with the FP32 r^2.  The
-// FP64 path decides in FP32 except inside a band of relative width 1e-4 around
-// (2h)^2 -- the FP32 r^2 of a pair near the cutoff is within ~3e-6 of the exact
-// one -- and recomputes r^2 in FP64 there, so its neighbour set is the exact
-// FP64 one.  A target far outside its cell (a clamped particle) takes the FP64
-// test for every candidate.  Hits enter a four-entry shift register that is
-// stored as one quad whenever it fills.
+// Candidates are read as FP32 offsets from their cell's origin (the cpos and
+// wcpos copies), U per lane in flight, with the index clamped instead of
+// branched.  A candidate is decided in FP32 except inside a band of relative
+// width 1e-4 around (2h + skin)^2 -- the FP32 r^2 of a pair near the cutoff is
+// within ~3e-6 of the exact one -- where r^2 is recomputed from the records:
+// in FP64 on the FP64 path, so its neighbour set is the exact FP64 one, and
+// from the fixed-point offsets on the mixed path (exact_r2).  On the FP64
+// path a target far outside its cell (a clamped particle) takes the FP64 test
+// for every candidate.  Hits enter a four-entry shift register that is stored
+// as one quad whenever it fills.
 template <int DIM, bool MIXED, int U>
 __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, int lk, int k,
-                                          const typename RV<DIM, MIXED>::real *pi, const float *ci,
+                                          const typename RV<DIM, MIXED>::real *pi, const double *qs,
+                                          const float *ci,
                                           const int *__restrict__ cstart, const int *__restrict__ wstart,
                                           const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
                                           const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
@@ -557,15 +650,22 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
                                           uint4 *__restrict__ nlist, int cap, int n)
 {
     using V = RV<DIM, MIXED>;
-    using VF = RV<DIM, true>;
     using real = typename V::real;
     const CellPos c = decode_cell(sc, I, lk);
     const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
+    // row culling: FP64 offsets on the FP64 path, the FP32 copies (metres) on
+    // the mixed path
     const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
-    const real cut2m = cull_margin<MIXED>(sc);
+    const real cut2m = MIXED ? (real)(sc.fbcut2 * (float)(1.0 + 1e-5)) : (real)(sc.bcut2 * (1.0 + 1e-9));
     const float fcs = sc.fcs, fcut2 = sc.fbcut2;       // the build radius (2h + skin)
     real o[3];
-    target_offsets<DIM, MIXED>(sc, I, c, pi, o);
+    if constexpr (MIXED) {
+        o[0] = ci[0];
+        o[1] = ci[1];
+        o[2] = ci[2];
+    } else {
+        target_offsets<DIM, MIXED>(sc, I, c, pi, o);
+    }
     float lo = fcut2 * (1.0f - 1e-4f), hi = fcut2 * (1.0f + 1e-4f);
     if constexpr (!MIXED) {
         bool far = false;
@@ -602,20 +702,11 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int s = min(t0 + u, s1 - 1);
-                        if constexpr (MIXED) {
-                            if (pass == 0) {
-                                const typename VF::v4 A = ld32(rec, 2 * s);
-                                cj[u][0] = A.x; cj[u][1] = A.y; cj[u][2] = DIM == 3 ? A.z : 0.0f;
-                            } else {
-                                VF::wall_pos(ld32(wpos, s), cj[u]);
-                            }
-                        } else {
-                            const typename Cand<DIM>::t w = pass == 0 ? ld32(cpos, s) : ld32(wcpos, s);
-                            cj[u][0] = w.x;
-                            cj[u][1] = w.y;
-                            if constexpr (DIM == 3) cj[u][2] = w.z;
-                            else cj[u][2] = 0.0f;
-                        }
+                        const typename Cand<DIM>::t w = pass == 0 ? ld32(cpos, s) : ld32(wcpos, s);
+                        cj[u][0] = w.x;
+                        cj[u][1] = w.y;
+                        if constexpr (DIM == 3) cj[u][2] = w.z;
+                        else cj[u][2] = 0.0f;
                     }
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
@@ -626,7 +717,11 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
                         const float r2f = norm2<DIM>(r);
                         bool hit = s < s1 && !(pass == 0 && s == k);
                         if constexpr (MIXED) {
-                            hit = hit && r2f < fcut2;
+                            hit = hit && r2f < hi;
+                            if (hit && !(r2f < lo)) {
+                                const typename V::v4 Aj = pass == 0 ? V::loadA(rec, s) : V::wall_A(wpos[s]);
+                                hit = exact_r2<DIM>(qs, Aj, rf.bits(s)) < sc.qbcut2;
+                            }
                         } else {
                             hit = hit && r2f < hi;
                             if (hit && !(r2f < lo)) {
@@ -666,23 +761,24 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
     return m;
 }
 
-// Phase 2: fn(wall, s, r, r2, A_j, B_j) for the first m (<= cap) entries of
-// target k; the records of U entries (U = 1, 2, 4, 8 or 16; above 4 a round
-// reads U / 4 quads) are fetched before any of them is used.
-// CHK: the list was built with a skin, so entries at 2h or beyond are skipped.
+// Phase 2: fn(wall, s, r, r2, A_j, B_j, e) for the first m (<= cap) entries
+// of target k; the records of U entries (U = 1, 2, 4, 8 or 16; above 4 a
+// round reads U / 4 quads) are fetched before any of them is used.
+// CHK: the list was built with a skin, so entries with r^2 >= cut2 are skipped.
 template <int DIM, bool MIXED, int U, int NEED, bool CHK = false, class Fn>
 __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
                                           const typename RV<DIM, MIXED>::real *pi,
                                           const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
                                           const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
-                                          const uint4 *__restrict__ nlist, int n, Fn &&fn)
+                                          const uint4 *__restrict__ nlist, int n,
+                                          typename RV<DIM, MIXED>::real cut2, Fn &&fn)
 {
     static_assert(U == 1 || U == 2 || U == 4 || U == 8 || U == 16, "entries come in quads");
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
     constexpr int QN = U > 4 ? U / 4 : 1;      // quads per round
-    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
+    const real cs = MIXED ? (real)1 : (real)sc.cs;
     for (int q0 = 0; q0 < m; q0 += 4 * QN) {
         unsigned eq[4 * QN];
 #pragma unroll
@@ -704,11 +800,7 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
                     const unsigned e = eq[h + u];
                     const int s = (int)(e & kSlotMask);
                     if (e & kWallBit) {             // position only, zero velocity
-                        const typename V::wpos_t w = ld32(wpos, s);
-                        A[u] = v4{};
-                        A[u].x = w.x;
-                        A[u].y = w.y;
-                        if constexpr (DIM == 3) A[u].z = w.z;
+                        A[u] = V::wall_A(ld32(wpos, s));
                         B[u] = v4{};
                     } else {
                         A[u] = ld32(rec, 2 * s);
@@ -733,8 +825,7 @@ __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
                     }
                     sub_vec<DIM>(t, pj, r);
                     const real r2 = norm2<DIM>(r);
-                    if (!CHK || r2 < (MIXED ? (real)sc.fcut2 : (real)sc.cut2))
-                        fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, r2, A[u], B[u]);
+                    if (!CHK || r2 < cut2) fn((e & kWallBit) != 0u, (int)(e & kSlotMask), r, r2, A[u], B[u], e);
                 }
             }
         }
@@ -779,7 +870,8 @@ template <int DIM, bool MIXED, int NEED, bool CHK, int R, class Fn>
 __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
                                           const typename RV<DIM, MIXED>::real *pi,
                                           const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
-                                          const uint4 *__restrict__ nlist, int n, Fn &&fn)
+                                          const uint4 *__restrict__ nlist, int n,
+                                          typename RV<DIM, MIXED>::real cut2, Fn &&fn)
 {
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
@@ -804,8 +896,7 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
     const char *base = reinterpret_cast<const char *>(rec);
     const uint32_t woff = (uint32_t)sc.wrec_off;
     const uint32_t p16 = (uint32_t)p * 16u;
-    const real cs = MIXED ? (real)sc.fcs : (real)sc.cs;
-    const real cut2 = MIXED ? (real)sc.fcut2 : (real)sc.cut2;
+    const real cs = MIXED ? (real)1 : (real)sc.cs;
     int mmax = m;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off, 64));
@@ -880,7 +971,7 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
                     }
                     sub_vec<DIM>(t, pj, r);
                     const real r2 = norm2<DIM>(r);
-                    if (!CHK || r2 < cut2) fn(wl, (int)(e & kSlotMask), r, r2, A, B);
+                    if (!CHK || r2 < cut2) fn(wl, (int)(e & kSlotMask), r, r2, A, B, e);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
@@ -892,12 +983,58 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
 // density sweep
 // ---------------------------------------------------------------------------
 
+// Candidate tests and list build alone (kSplitBuild): lists of every target
+// and their lengths (lcount); a list longer than cap raises
+// SPH_FLAG_CAPACITY (its target searches the cells in the sweeps).  SKIN:
+// with radius 2h + skin, on build steps only (*gate != 0).
+template <int DIM, bool MIXED, bool SKIN, int PF>
+__global__ __launch_bounds__(kMaxBlock) void k_build(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ cstart, const int *__restrict__ wstart,
+    const typename Rec<DIM, MIXED>::v4 *__restrict__ rec, const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos,
+    const typename Cand<DIM>::t *__restrict__ cpos, const typename Cand<DIM>::t *__restrict__ wcpos,
+    uint4 *__restrict__ nlist, int *__restrict__ lcount, int cap, unsigned *__restrict__ flags,
+    const int *__restrict__ gate)
+{
+    using V = RV<DIM, MIXED>;
+    using real = typename V::real;
+    using v4 = typename V::v4;
+    if constexpr (SKIN) {
+        if (*gate == 0) return;
+    }
+    const Chunk ch = map[blockIdx.x];
+    const int k = ch.begin + threadIdx.x;
+    if (k >= ch.end) return;
+    const InstDev &I = inst[ch.inst];
+    const int lk = skey[k] - I.cell_base;
+    const v4 Ai = V::loadA(rec, k);
+    real pi[3];
+    V::pos(Ai, pi);
+    double qs[3] = {0.0, 0.0, 0.0};
+    if constexpr (MIXED) {
+        int qi[3];
+        V::qpos(Ai, qi);
+        exact_target<DIM>(qi, qs);
+    }
+    float ci[3];
+    const typename Cand<DIM>::t cp = cpos[k];
+    ci[0] = cp.x;
+    ci[1] = cp.y;
+    if constexpr (DIM == 3) ci[2] = cp.z;
+    else ci[2] = 0.0f;
+    const int m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, qs, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+                                             nlist, cap, sc.N);
+    lcount[k] = m;
+    if (m > cap) atomicOr(flags, 4u);
+}
+
 // LIST = 0: direct search.  LIST = 1: build the list, then walk it.  LIST = 2
 // (Verlet skin): build the list with radius 2h + skin when the previous
 // step's reduction asked for a rebuild (*gate != 0), else walk the list of the
 // last build; entries at 2h or beyond are skipped.  LIST = 3: that walk alone,
-// in a kernel of its own (launched after LIST = 2; each returns at once on the
-// steps that belong to the other).
+// in a kernel of its own (launched after LIST = 2, or after k_build on every
+// step with kSplitBuild).  LIST = 5: the walk of a list without a skin, after
+// k_build.
 template <int DIM, bool MIXED, int LIST, int PF>
 __global__ __launch_bounds__(kMaxBlock) void k_density(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
@@ -917,7 +1054,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     if constexpr (LIST == 2 && kSkinSplitWalk) {
         if (*gate == 0) return;
     }
-    if constexpr (LIST == 3) {
+    if constexpr (LIST == 3 && !kSplitBuild) {
         if (*gate != 0) return;
     }
     // the cooperative walk needs every lane of the wave, targets or not
@@ -935,29 +1072,49 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     real pi[3], vi[3];
     V::pos(Ai, pi);
     V::vel(Ai, Bi, vi);
-    const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
-    const real kW = MIXED ? (real)sc.fkW : (real)sc.kW;
-    const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
-    real sigma = MIXED ? (real)0 : (real)sc.W0;
+    double qs[3] = {0.0, 0.0, 0.0};
+    if constexpr (MIXED) {
+        int qi[3];
+        V::qpos(Ai, qi);
+        exact_target<DIM>(qi, qs);
+    }
+    // the summation density in FP64 on both paths (see exact_r2)
+    double sigma = MIXED ? 0.0 : sc.W0;
     real drho = 0;
     int cnt = 0;
-    auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj)
+    const real cut2 = walk_cut2<MIXED, true>(sc);
+    auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj, unsigned e)
         __attribute__((always_inline)) {
         (void)wall;                        // wall records carry zero velocity
-        real W, F;
-        kernel_WF(r2, inv_h, kW, kF, W, F);
         real vj[3];
         V::vel(Aj, Bj, vj);
         real vr = (vi[0] - vj[0]) * r[0] + (vi[1] - vj[1]) * r[1];
         if constexpr (DIM == 3) vr += (vi[2] - vj[2]) * r[2];
-        sigma += W;
-        drho += vr * F;
-        ++cnt;
+        if constexpr (MIXED) {
+            // exact pair test and kernel value on the fixed-point positions;
+            // the continuity term in FP32 (lengths in units of cs)
+            const double r2q = exact_r2<DIM>(qs, Aj, e);
+            if (r2q < sc.qcut2) {
+                double W;
+                float F;
+                kernel_WF_exact(r2q, sc.qinv_h, sc.kW, sc.kF, W, F);
+                sigma += W;
+                drho += vr * F;
+                ++cnt;
+            }
+        } else {
+            (void)e;
+            real W, F;
+            kernel_WF(r2, (real)sc.inv_h, (real)sc.kW, (real)sc.kF, W, F);
+            sigma += W;
+            drho += vr * F;
+            ++cnt;
+        }
     };
-    if constexpr (COOP && LIST == 3) {
+    if constexpr (COOP && (LIST == 3 || LIST == 5)) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED, true, kCoopRoundsWalk>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
-        if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        walk_coop<DIM, MIXED, NEED, LIST == 3, kCoopRoundsWalk>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
+        if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         if (!act) return;
     } else if constexpr (COOP) {
         // candidate tests per target, then the cooperative walk with every lane
@@ -966,64 +1123,58 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         if (act) {
             if (build) {
                 float ci[3];
-                if constexpr (MIXED) {
-                    ci[0] = pi[0]; ci[1] = pi[1]; ci[2] = pi[2];
-                } else {
-                    const typename Cand<DIM>::t cp = cpos[k];
-                    ci[0] = cp.x; ci[1] = cp.y;
-                    if constexpr (DIM == 3) ci[2] = cp.z;
-                    else ci[2] = 0.0f;
-                }
-                m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+                const typename Cand<DIM>::t cp = cpos[k];
+                ci[0] = cp.x; ci[1] = cp.y;
+                if constexpr (DIM == 3) ci[2] = cp.z;
+                else ci[2] = 0.0f;
+                m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, qs, ci, cstart, wstart, rec, wpos, cpos, wcpos,
                                                nlist, cap, n);
                 lcount[k] = m;
             } else {
                 m = lcount[k];
             }
         }
-        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsBuild>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsBuild>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
         if (act && m > cap) {
             if (build) atomicOr(flags, 4u);
-            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         }
         if (!act) return;
-    } else if constexpr (LIST == 3) {
+    } else if constexpr (LIST == 3 || LIST == 5) {
         const int m = lcount[k];
-        if (m <= cap) walk_list<DIM, MIXED, skin_walk_u<DIM, MIXED>(), NEED, true>(sc, k, m, pi, rec, wpos, nlist, n, pair);
-        else for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        if (m <= cap) walk_list<DIM, MIXED, skin_walk_u<DIM, MIXED>(), NEED, LIST == 3>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
+        else for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
     } else if constexpr (LIST) {
         float ci[3];
-        if constexpr (MIXED) {
-            ci[0] = pi[0]; ci[1] = pi[1]; ci[2] = pi[2];
-        } else {
-            const typename Cand<DIM>::t cp = cpos[k];
-            ci[0] = cp.x; ci[1] = cp.y;
-            if constexpr (DIM == 3) ci[2] = cp.z;
-            else ci[2] = 0.0f;
-        }
+        const typename Cand<DIM>::t cp = cpos[k];
+        ci[0] = cp.x; ci[1] = cp.y;
+        if constexpr (DIM == 3) ci[2] = cp.z;
+        else ci[2] = 0.0f;
         const bool build = LIST == 1 || *gate != 0;
         int m;
         if (build) {
-            m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+            m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, qs, ci, cstart, wstart, rec, wpos, cpos, wcpos,
                                            nlist, cap, n);
             lcount[k] = m;
         } else {
             m = lcount[k];
         }
         if (m <= cap) {
-            walk_list<DIM, MIXED, fused_walk_u<MIXED>(), NEED, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
+            walk_list<DIM, MIXED, fused_walk_u<MIXED>(), NEED, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
         } else {
             if (build) atomicOr(flags, 4u);
-            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         }
     } else {
-        for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
     }
     const int i = perm[k];
-    const double sig = MIXED ? sc.W0 + (double)sigma : (double)sigma;
+    const double sig = MIXED ? sc.W0 + sigma : sigma;
     const double rho_sum = sc.mass * sig;
     const double dtb = use_dt ? dt[ch.inst] : 0.0;
-    const double rho_star = rho[i] + dtb * (sc.mass * (double)drho);
+    // mixed path: the continuity sum is in units of cs
+    const double mscale = MIXED ? sc.mass * sc.cs : sc.mass;
+    const double rho_star = rho[i] + dtb * (mscale * (double)drho);
     const double excess = rho_star - rho_sum;
     const double rn = excess > 0.0 ? rho_sum + excess * sc.rho0 / rho_star : rho_sum;
     double p = I.c0 * I.c0 * (rn - sc.rho0);
@@ -1048,11 +1199,31 @@ static void density_dispatch(const SimConst &sc, const Dev &d, int use_dt, hipSt
         d.list_cap, d.flags, d.gate);
 }
 
+template <int DIM, bool MIXED, bool SKIN, int PF>
+static void build_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    using R = Rec<DIM, MIXED>;
+    k_build<DIM, MIXED, SKIN, PF><<<d.nfchunks, d.block, 0, s>>>(
+        sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, static_cast<const typename R::v4 *>(d.rec),
+        static_cast<const typename R::wpos_t *>(d.wpos), static_cast<const typename Cand<DIM>::t *>(d.cpos),
+        static_cast<const typename Cand<DIM>::t *>(d.wcpos), d.nlist, d.lcount, d.list_cap, d.flags, d.gate);
+}
+
 template <int DIM, bool MIXED>
 static void density_variant(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
 {
     if (d.list_cap <= 0) density_dispatch<DIM, MIXED, 0, 4>(sc, d, use_dt, s);
-    else if (d.gate) {
+    else if (kSplitBuild) {
+        if (d.gate) {
+            if (d.prefetch == 4) build_dispatch<DIM, MIXED, true, 4>(sc, d, s);
+            else build_dispatch<DIM, MIXED, true, 8>(sc, d, s);
+            density_dispatch<DIM, MIXED, 3, 4>(sc, d, use_dt, s);
+        } else {
+            if (d.prefetch == 4) build_dispatch<DIM, MIXED, false, 4>(sc, d, s);
+            else build_dispatch<DIM, MIXED, false, 8>(sc, d, s);
+            density_dispatch<DIM, MIXED, 5, 4>(sc, d, use_dt, s);
+        }
+    } else if (d.gate) {
         if (d.prefetch == 4) density_dispatch<DIM, MIXED, 2, 4>(sc, d, use_dt, s);
         else density_dispatch<DIM, MIXED, 2, 8>(sc, d, use_dt, s);
         if (kSkinSplitWalk) density_dispatch<DIM, MIXED, 3, 4>(sc, d, use_dt, s);
@@ -1102,16 +1273,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     const real rho_i = V::rho(Bi), P_i = V::P(Bi);
     const real p_i = P_i * rho_i * rho_i;
     const real inv_rho_i2 = (real)1 / (rho_i * rho_i);
-    const real inv_h = MIXED ? (real)sc.finv_h : (real)sc.inv_h;
+    // mixed path: lengths in units of cs (the sums are scaled back below)
+    const real inv_h = MIXED ? (real)sc.uinv_h : (real)sc.inv_h;
     const real kF = MIXED ? (real)sc.fkF : (real)sc.kF;
-    const real visc_a = (real)(sc.alpha * I.c0 * sc.h);
-    const real eps_h2 = MIXED ? (real)sc.feps_h2 : (real)sc.eps_h2;
-    const real gx = MIXED ? (real)sc.fg[0] : (real)sc.g[0];
-    const real gy = MIXED ? (real)sc.fg[1] : (real)sc.g[1];
-    const real gz = MIXED ? (real)sc.fg[2] : (real)sc.g[2];
+    const real visc_a = MIXED ? (real)(sc.uvisc_scale * (float)I.c0) : (real)(sc.alpha * I.c0 * sc.h);
+    const real eps_h2 = MIXED ? (real)sc.ueps_h2 : (real)sc.eps_h2;
+    const real gx = MIXED ? (real)sc.ug[0] : (real)sc.g[0];
+    const real gy = MIXED ? (real)sc.ug[1] : (real)sc.g[1];
+    const real gz = MIXED ? (real)sc.ug[2] : (real)sc.g[2];
+    const real cut2 = walk_cut2<MIXED>(sc);
     real acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
     int cnt = 0;
-    auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj)
+    auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj, unsigned)
         __attribute__((always_inline)) {
         // branch-free: lanes of a wave mix fluid and wall sources
         real F;
@@ -1143,17 +1316,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, coop_rounds_force<DIM, MIXED>()>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, coop_rounds_force<DIM, MIXED>()>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
         if (act && m > cap)
-            for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
+            for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, cut2, pair);
     } else if (act) {
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
-            if (m <= cap) walk_list<DIM, MIXED, U, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
-            else for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+            if (m <= cap) walk_list<DIM, MIXED, U, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
+            else for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         } else {
-            for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+            for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         }
     }
     double vals[kNPart];
@@ -1161,12 +1334,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     for (int q = 0; q < kNPart; ++q) vals[q] = 0.0;
     if (act) {
         const int i = perm[k];
+        const double mscale = MIXED ? sc.mass * sc.cs : sc.mass;
         double an[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            an[c] = sc.g[c] + sc.mass * (double)acc[c];
+            an[c] = sc.g[c] + mscale * (double)acc[c];
             a[(int64_t)c * n + i] = an[c];
-            vals[P_FF + c] = sc.mass * (sc.mass * (double)aff[c]);
+            vals[P_FF + c] = sc.mass * (mscale * (double)aff[c]);
         }
         vals[P_PAIRS] = (double)cnt;
         if constexpr (FUSED) {
@@ -1374,7 +1548,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     const double c0 = I.c0, inv_c0 = 1.0 / c0;
     double acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
     int cnt = 0;
-    auto pair = [&](bool wall, int, const double *r, double r2, const v4 &Aj, const v4 &Bj)
+    auto pair = [&](bool wall, int, const double *r, double r2, const v4 &Aj, const v4 &Bj, unsigned)
         __attribute__((always_inline)) {
         DualPair<DIM> q;
         dual_pair<DIM>(sc, wall, r, r2, vi, rho_i, p_i, Aj, Bj, q);
@@ -1397,17 +1571,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     if constexpr (LIST && kCoopWalk) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, sc.cut2, pair);
         if (act && m > cap)
-            for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, pair);
+            for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
     } else if (act) {
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
-            if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
-            else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+            if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, sc.cut2, pair);
+            else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
         } else {
-            for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+            for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
         }
     }
     double vals[kNPart];
@@ -1456,7 +1630,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const double rho_i = V::rho(Bi), p_i = V::P(Bi);
     const double c0 = I.c0;
     double sum = 0.0;
-    auto pair = [&](bool wall, int, const double *r, double r2, const v4 &Aj, const v4 &Bj)
+    auto pair = [&](bool wall, int, const double *r, double r2, const v4 &Aj, const v4 &Bj, unsigned)
         __attribute__((always_inline)) {
         DualPair<DIM> q;
         dual_pair<DIM>(sc, wall, r, r2, vi, rho_i, p_i, Aj, Bj, q);
@@ -1475,15 +1649,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const int lk = skey[kk] - I.cell_base;
     if constexpr (LIST && kCoopWalk) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, pair);
-        if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, sc.cut2, pair);
+        if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
         if (!act) return;
     } else if constexpr (LIST) {
         const int m = lcount[k];
-        if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, pair);
-        else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, sc.cut2, pair);
+        else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
     } else {
-        for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, pair);
+        for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
     }
     const int i = perm[k];
     const double d = 2.0 * rho_i * (sc.mass * sum);

@@ -66,6 +66,32 @@ def errors(g, r, x0, rho0=1000.0):
     return e
 
 
+# The method's gates (relative errors of density, velocity and position on
+# the probe set): 1e-5 after one step, 1e-3 after 100 steps.  The mixed path
+# is held to them; the FP64 path to far tighter bounds in each test.
+GATE_1_STEP = 1e-5
+GATE_100_STEPS = 1e-3
+
+
+def total_energy(x, v, rho, mass, c0, g, rho0=1000.0):
+    """Kinetic + potential + internal energy of one instance's fluid state
+    (x, v: (n, dim); internal energy of the clipped equation of state,
+    m c0^2 (ln(rho/rho0) + rho0/rho - 1) for rho > rho0), summed on the host in
+    one fixed order so that two states differ only by their values."""
+    dim = x.shape[1]
+    ke = 0.5 * mass * np.sum(v * v, axis=1)
+    pe = -mass * (x @ np.asarray(g, dtype=np.float64)[:dim])
+    ie = np.where(rho > rho0, mass * c0 * c0 * (np.log(rho / rho0) + rho0 / rho - 1.0), 0.0)
+    return float(np.sum(ke + pe + ie)), float(np.sum(ke))
+
+
+def energy_error(g, r, mass, c0, gvec, rho0=1000.0):
+    """|E_G - E_ref| / KE_ref for two views of the same instance."""
+    eg, _ = total_energy(g["x"], g["v"], g["rho"], mass, c0, gvec, rho0)
+    er, ke = total_energy(r["x"], r["v"], r["rho"], mass, c0, gvec, rho0)
+    return abs(eg - er) / ke if ke > 0 else abs(eg - er)
+
+
 def integer_mismatches(g, r):
     out = {}
     for k in ("key", "perm", "sorted_ids", "cell_start", "wall_start", "wall_perm", "count"):
