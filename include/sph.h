@@ -32,8 +32,9 @@
  *     failed call leaves a message in sph_last_error() (per host thread).
  *   - Device pointers are caller-owned (allocated by the caller, e.g. torch).
  *     The library allocates no device memory: scratch lives in the caller's
- *     workspace of sph_workspace_size() bytes.  Pointers passed to sph_bind
- *     must stay valid until sph_destroy or the next sph_bind.
+ *     workspace of sph_workspace_size() bytes, or, for small cases bound with
+ *     sph_bind_static, in a static device array of the library.  Pointers
+ *     passed to sph_bind must stay valid until sph_destroy or the next bind.
  *   - Stage calls are stream-ordered and asynchronous; argument errors are
  *     reported synchronously; device-side conditions set sticky flags read by
  *     sph_poll_errors.  One context per stream / host thread at a time.
@@ -77,8 +78,11 @@ typedef enum {
 
 typedef enum {
     SPH_FP64 = 0,            /* all arithmetic in FP64 */
-    SPH_MIXED = 1            /* FP32 pair sweeps on FP32 offsets from FP64 cell
-                                origins; FP64 state, integration and reductions */
+    SPH_MIXED = 1            /* pair sweeps on 32-bit fixed-point offsets from
+                                the cell centres: FP32 force and continuity
+                                sums, the summation density in FP64 from exact
+                                pair differences; FP64 state, integration and
+                                reductions */
 } sph_precision;
 
 /* Per-instance diagnostics, SPH_NDIAG doubles per instance, written by the
@@ -223,6 +227,24 @@ sph_status sph_workspace_size(const sph_ctx *ctx, size_t *bytes);
  * table: wall keys, the stable sort of walls by cell (wall_perm), wall_start
  * and the sorted wall records.  Synchronises `stream` before returning. */
 sph_status sph_bind(sph_ctx *ctx, const sph_buffers *b, void *stream);
+
+/* Bytes of the library-owned workspace behind sph_bind_static (per device). */
+#define SPH_STATIC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sph_bind
+ * with the library's own workspace, a static device array of
+ * SPH_STATIC_SCRATCH_BYTES bytes that every device using the library holds
+ * until the process ends, in place of b->workspace (ignored; may be NULL).
+ * The caller still passes every input and output buffer.  Calls no
+ * allocating routine.  Fails with SPH_E_CAPACITY, before touching the device,
+ * when sph_workspace_size() exceeds SPH_STATIC_SCRATCH_BYTES (about 100 k
+ * particles of the small cases).  All contexts bound this way on one device
+ * share that array: binding another context overwrites the state of the
+ * previous one, and contexts used at the same time on one device race.
+ * Everything a step needs to start from zero is cleared by the bind and the
+ * prime, as for a caller workspace.  Synchronises `stream` before returning. */
+sph_status sph_bind_static(sph_ctx *ctx, const sph_buffers *b, void *stream);
 
 /* Step 0: cell table at the current positions, density with dt = 0 (so
  * rho <- rho_sum + max(0, rho - rho_sum) rho0/rho), forces, reductions.  Gives

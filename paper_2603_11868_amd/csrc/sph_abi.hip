@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -740,6 +741,55 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     c->steps_done = 0;
     c->substeps_done = 0;
     return SPH_OK;
+}
+
+// Workspace owned by the library for callers that cannot allocate device
+// memory (sph_bind_static).  Each device that loads the library holds its own
+// copy until the process ends.  In host code the name stands for a host-side
+// shadow, not for device memory: only the address that hipGetSymbolAddress
+// returns for the current device is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[SPH_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+sph_status static_scratch_address(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPH_E_UNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(SPH_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPH_OK;
+}
+
+}  // namespace
+
+sph_status sph_bind_static(sph_ctx *c, const sph_buffers *b, void *stream)
+{
+    if (!c || !b) return fail(SPH_E_ARG, "null argument");
+    if (c->ws_bytes > (size_t)SPH_STATIC_SCRATCH_BYTES)
+        return fail(SPH_E_CAPACITY, "workspace of " + std::to_string(c->ws_bytes) +
+                                        " bytes exceeds the static scratch of " +
+                                        std::to_string((size_t)SPH_STATIC_SCRATCH_BYTES) +
+                                        " bytes; use sph_bind with a caller workspace");
+    void *ws = nullptr;
+    const sph_status st = static_scratch_address(&ws);
+    if (st != SPH_OK) return st;
+    sph_buffers bb = *b;
+    bb.workspace = ws;
+    return sph_bind(c, &bb, stream);
 }
 
 sph_status sph_prime(sph_ctx *c, void *stream)

@@ -36,7 +36,9 @@ SYMBOLS = ("sph_last_error", "sph_create", "sph_destroy", "sph_get_info", "sph_g
            "sph_workspace_size", "sph_bind", "sph_prime", "sph_build_cells", "sph_sort",
            "sph_density", "sph_forces", "sph_integrate", "sph_step_batched",
            "sph_poll_errors", "sph_set_timing", "sph_stage_times", "sph_stage_name",
-           "sph_stage_count", "sph_substeps", "sph_cell_builds", "sph_set_timing_mask")
+           "sph_stage_count", "sph_substeps", "sph_cell_builds", "sph_set_timing_mask",
+           "sph_bind_static")
+SPH_STATIC_SCRATCH_BYTES = 32 << 20
 
 SPH_SCHEME_WCSPH, SPH_SCHEME_DUAL = 0, 1
 SPH_KEYS_ROW_MAJOR, SPH_KEYS_MORTON_TILES = 0, 1
@@ -103,6 +105,7 @@ def lib():
                                    C.POINTER(C.c_int32)]
         L.sph_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.sph_bind.argtypes = [vp, C.POINTER(sph_buffers), vp]
+        L.sph_bind_static.argtypes = [vp, C.POINTER(sph_buffers), vp]
         for n in ("sph_prime", "sph_build_cells", "sph_density", "sph_forces"):
             getattr(L, n).argtypes = [vp, vp]
         L.sph_sort.argtypes = [vp, C.c_int32, vp]
@@ -178,6 +181,10 @@ def sph_workspace_size(ctx) -> int:
 
 def sph_bind(ctx, buffers: sph_buffers, stream=None):
     _check(lib().sph_bind(ctx, C.byref(buffers), _stream(stream)))
+
+
+def sph_bind_static(ctx, buffers: sph_buffers, stream=None):
+    _check(lib().sph_bind_static(ctx, C.byref(buffers), _stream(stream)))
 
 
 def sph_prime(ctx, stream=None):
@@ -262,7 +269,7 @@ class Simulation:
     def __init__(self, case, precision="fp64", reorder_every=None, block_threads=0,
                  use_graph=False, device="cuda", alpha=None, g=None,
                  cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0,
-                 scheme="wcsph", skin=0.0, key_order="row"):
+                 scheme="wcsph", skin=0.0, key_order="row", static_scratch=False):
         import torch
         self.torch = torch
         self.case = case
@@ -339,9 +346,14 @@ class Simulation:
         self.wall_start = torch.zeros(Cn + 1, dtype=i32, device=dev)
         self.dt = torch.zeros(B, dtype=f64, device=dev)
         self.diag = torch.zeros((B, SPH_NDIAG), dtype=f64, device=dev)
-        self.workspace = torch.empty(int(info.workspace_bytes) + 256, dtype=torch.uint8, device=dev)
-        wptr = self.workspace.data_ptr()
-        wptr = (wptr + 255) & ~255
+        if static_scratch:
+            # the library's own workspace (sph_bind_static): nothing allocated here
+            self.workspace = None
+            wptr = 0
+        else:
+            self.workspace = torch.empty(int(info.workspace_bytes) + 256, dtype=torch.uint8, device=dev)
+            wptr = self.workspace.data_ptr()
+            wptr = (wptr + 255) & ~255
         bufs = sph_buffers()
         ptr = lambda t: C.c_void_p(t.data_ptr()) if t.numel() else C.c_void_p(0)
         bufs.x, bufs.v, bufs.a, bufs.rho = ptr(self.x), ptr(self.v), ptr(self.a), ptr(self.rho)
@@ -351,7 +363,10 @@ class Simulation:
         bufs.dt, bufs.diag = ptr(self.dt), ptr(self.diag)
         bufs.workspace = C.c_void_p(wptr)
         self.buffers = bufs
-        sph_bind(self.ctx, bufs)
+        if static_scratch:
+            sph_bind_static(self.ctx, bufs)
+        else:
+            sph_bind(self.ctx, bufs)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

@@ -224,3 +224,25 @@ def test_key_order_option(sphmod):
     p, descs = _params(sphmod, case, key_order=5)
     with pytest.raises(sphmod.SphError, match="E_ARG"):
         sphmod.sph_create(p)
+
+
+def test_bind_static_rejects_workspaces_beyond_its_scratch(sphmod):
+    """sph_bind_static checks the workspace size against the static scratch
+    before it touches the device: the 2.0 M-particle case needs far more."""
+    case = dambreak.make_case("c2_3d")
+    p, descs = _params(sphmod, case)
+    ctx = sphmod.sph_create(p)
+    try:
+        assert sphmod.sph_workspace_size(ctx) > sphmod.SPH_STATIC_SCRATCH_BYTES
+        bufs = sphmod.sph_buffers()
+        with pytest.raises(sphmod.SphError, match="SPH_E_CAPACITY.*static scratch"):
+            sphmod.sph_bind_static(ctx, bufs, stream=0)
+    finally:
+        sphmod.sph_destroy(ctx)
+
+
+def test_static_scratch_size_matches_header(sphmod):
+    with open(os.path.join(ROOT, "include", "sph.h")) as f:
+        text = f.read()
+    m = re.search(r"#define SPH_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == sphmod.SPH_STATIC_SCRATCH_BYTES
