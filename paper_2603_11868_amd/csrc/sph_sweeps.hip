@@ -37,6 +37,8 @@ constexpr bool kSkinSplitWalk = true;
 // density walk after it: the build then runs at the occupancy of its own
 // registers, not at that of the FP64 density sums.
 constexpr bool kSplitBuild = true;
+// The split build as cell pairs (k_build_cp; row-major keys).
+constexpr bool kCellPairBuild = true;
 // List walks gather records cooperatively (walk_coop).
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
@@ -983,11 +985,316 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
 // density sweep
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Cell-pair list build.
+//
+// The lanes of a wave hold 64 sources, the targets are taken one at a time:
+// a wave owns 64 consecutive targets (sorted slots) and walks them cell by
+// cell.  For one cell, the sources of its 3^d stencil -- rows in z, y order,
+// per row the fluid slots of its three cells, then their wall slots, the
+// order of the direct search -- form one sequence, of which lane l of
+// register chunk j holds element 64 j + l: its FP32 cell offset shifted into
+// the frame of the target cell, and its list entry.  Each target of the cell
+// (wave-uniform, so its offsets are scalar operands) then tests a chunk with
+// one compare per lane; the hits append to the target's list in lane, that is
+// slot, order through a ballot and mbcnt, into a staging area in LDS that is
+// written out as quads when the target is done.  Every candidate test costs
+// about a dozen VALU instructions per 64 pairs, where a lane per target costs
+// about two dozen per pair; source loads happen once per cell, not once per
+// target.  The decisions are those of build_list (FP32 test, exact recheck in
+// the band around (2h + skin)^2), so the lists are identical.
+//
+// Cells whose stencil holds more than cp_chunks() * 64 sources mark their
+// targets (lcount = -1) for k_build, which follows with FALLBACK = true and
+// builds only those; tiled Morton keys (stencil rows not contiguous) and
+// capacities above kCpListMax use k_build alone.
+// ---------------------------------------------------------------------------
+
+template <int DIM> constexpr int cp_chunks() { return DIM == 3 ? 10 : 4; }   // register chunks of 64 sources
+constexpr int kCpListMax = 255;        // list capacity the cell-pair build supports
+constexpr int kCpBandMax = 63;         // band hits of one target awaiting the exact test
+
+// Value of `v` on lane `src` (lane-varying source lane).
+__device__ __forceinline__ int lane_value(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+
+template <int DIM, bool MIXED, bool SKIN>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_build_cp(
+    SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
+    const int *__restrict__ skey, const int *__restrict__ cstart, const int *__restrict__ wstart,
+    const typename Rec<DIM, MIXED>::v4 *__restrict__ rec, const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos,
+    const typename Cand<DIM>::t *__restrict__ cpos, uint32_t wcpos_off,
+    uint4 *__restrict__ nlist, int *__restrict__ lcount, int cap, unsigned *__restrict__ flags,
+    const int *__restrict__ gate)
+{
+    using V = RV<DIM, MIXED>;
+    using CT = typename Cand<DIM>::t;
+    constexpr int NR = DIM == 3 ? 18 : 6;                 // (row, kind) ranges of a stencil
+    if constexpr (SKIN) {
+        if (*gate == 0) return;
+    }
+    constexpr int CH = cp_chunks<DIM>();
+    // staging: a whole stencil of hits, and room past it for the writes of
+    // the lanes without a hit
+    constexpr int kCpStage = CH * 64;
+    __shared__ __align__(16) unsigned stage[kMaxBlock / 64][kCpStage + 128];
+    __shared__ int bands[kMaxBlock / 64][kCpBandMax + 1];
+    const Chunk ch = map[blockIdx.x];
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w0 = ch.begin + wv * 64;
+    const int w1 = min(w0 + 64, ch.end);
+    if (w0 >= w1) return;                                 // the whole wave
+    unsigned *lst = stage[wv];
+    int *bnd = bands[wv];
+    const InstDev &I = inst[ch.inst];
+    const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
+    const float fcs = sc.fcs;
+    const float blo = sc.fbcut2 * (1.0f - 1e-4f), bhi = sc.fbcut2 * (1.0f + 1e-4f);
+    const float bw = sc.fbcut2 * 1e-4f;                   // half width of that band
+    const char *cbase = reinterpret_cast<const char *>(cpos);
+    const int n = sc.N;
+    int t0 = w0;
+    while (t0 < w1) {
+        const int key = __builtin_amdgcn_readfirstlane(skey[t0]);
+        const int t1 = min(w1, __builtin_amdgcn_readfirstlane(cstart[key + 1]));
+        const int lk = key - I.cell_base;
+        const int cx = lk % ncx, cy = (lk / ncx) % ncy, cz = lk / (ncx * ncy);
+        // lane r < NR describes range r = 2 row + kind: its first slot, length,
+        // the slots where the second and third cell of the row begin, and the
+        // row's cell offsets (x of its first cell, y, z; each plus one)
+        int rstart = 0, rlen = 0, rb1 = 0, rb2 = 0, rsh = 0;
+        if (lane < NR) {
+            const int row = lane >> 1, kind = lane & 1;
+            const int dy = (DIM == 3 ? row % 3 : row) - 1;
+            const int dz = DIM == 3 ? row / 3 - 1 : 0;
+            const int yy = cy + dy, zz = cz + dz;
+            const int xlo = cx > 0 ? cx - 1 : cx, xhi = cx < ncx - 1 ? cx + 1 : cx;
+            if (yy >= 0 && yy < ncy && zz >= 0 && zz < ncz) {
+                const int *st = kind ? wstart : cstart;
+                const int rk = I.cell_base + (yy + ncy * zz) * ncx;
+                rstart = st[rk + xlo];
+                const int rend = st[rk + xhi + 1];
+                rlen = rend - rstart;
+                rb1 = xlo + 1 <= xhi ? st[rk + xlo + 1] : rend;
+                rb2 = xlo + 2 <= xhi ? st[rk + xlo + 2] : rend;
+            }
+            rsh = (xlo - cx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4) | (kind << 6);
+        }
+        const int rend_seq = wave_inclusive_scan(rlen);  // end of range r in the sequence
+        const int S = __builtin_amdgcn_readlane(rend_seq, 63);
+        const int nch = (S + 63) >> 6;
+        if (nch > CH) {
+            // too many sources for the registers: k_build takes these targets
+            if (lane < t1 - t0) lcount[t0 + lane] = -1;
+            t0 = t1;
+            continue;
+        }
+        // the chunks: source positions in the frame of the target cell, and entries
+        float px[CH], py[CH], pz[CH];
+        unsigned ent[CH];
+        int rc = 0;                                       // ranges ending at or before 64 j
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            px[j] = py[j] = pz[j] = 3.0e38f;
+            ent[j] = 0u;
+            if (j < nch) {
+                const int g = 64 * j + lane;
+                while (rc < NR && __builtin_amdgcn_readlane(rend_seq, rc) <= 64 * j) ++rc;
+                // the range of g: rc plus the ranges ending inside the chunk at or before g
+                int r = rc;
+                for (int q = rc; q < NR; ++q) {
+                    const int e = __builtin_amdgcn_readlane(rend_seq, q);
+                    if (e > 64 * j + 63) break;
+                    r += e <= g ? 1 : 0;
+                }
+                const int pre = lane_value(rend_seq - rlen, r);
+                const int slot = lane_value(rstart, r) + (g - pre);
+                const int sh = lane_value(rsh, r);
+                const int ox = (sh & 3) - 1 + (slot >= lane_value(rb1, r) ? 1 : 0) + (slot >= lane_value(rb2, r) ? 1 : 0);
+                const int oy = ((sh >> 2) & 3) - 1, oz = ((sh >> 4) & 3) - 1;
+                const bool wall = (sh >> 6) & 1;
+                const bool valid = g < S;
+                const uint32_t off = valid ? (wall ? wcpos_off : 0u) + (uint32_t)slot * (uint32_t)sizeof(CT) : 0u;
+                const CT c = *reinterpret_cast<const CT *>(cbase + off);
+                if (valid) {
+                    px[j] = fmaf((float)ox, fcs, c.x);
+                    py[j] = fmaf((float)oy, fcs, c.y);
+                    if constexpr (DIM == 3) pz[j] = fmaf((float)oz, fcs, c.z);
+                    else pz[j] = 0.0f;
+                    ent[j] = (wall ? kWallBit : 0u) | (unsigned)slot | (MIXED ? offset_bits(ox, oy, oz) : 0u);
+                }
+            }
+        }
+        for (int t = t0; t < t1; ++t) {
+            const CT ot = cpos[t];
+            const float ox_t = ot.x, oy_t = ot.y;
+            float oz_t = 0.0f;
+            if constexpr (DIM == 3) oz_t = ot.z;
+            // a target far outside its cell (a clamped key): k_build, which
+            // decides such a target's candidates in FP64
+            if (fabsf(ox_t) > 4.0f * fcs || fabsf(oy_t) > 4.0f * fcs || fabsf(oz_t) > 4.0f * fcs) {
+                if (lane == 0) lcount[t] = -1;
+                continue;
+            }
+            // the target's own entry: the one hit at r^2 = 0 that is not a pair
+            const unsigned eself = (unsigned)t | (MIXED ? offset_bits(0, 0, 0) : 0u);
+            // the chunks against target t: every hit is staged (the staging area
+            // holds a whole stencil), with no exec mask change in the loop.
+            // RECORD: also note the list positions of the hits inside the band
+            // around the build radius, for the exact test below.
+            auto sweep = [&](auto record, int &m, int &nb) __attribute__((always_inline)) {
+                constexpr bool RECORD = decltype(record)::value;
+                uint64_t bandacc = 0;                     // lanes with an r^2 near the build radius
+                m = 0;
+                nb = 0;
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    if (j < nch) {
+                        const float dx = ox_t - px[j], dy = oy_t - py[j], dz = oz_t - pz[j];
+                        float r2 = dx * dx + dy * dy;
+                        if constexpr (DIM == 3) r2 += dz * dz;
+                        const bool h = r2 < bhi;
+                        const uint64_t hm = __builtin_amdgcn_ballot_w64(h);
+                        int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+                        // every lane writes: a hit at its place in the list, any other
+                        // lane past the places this chunk's hits can take (later hits
+                        // overwrite it, or it lies past the list)
+                        asm volatile("" : "+v"(pos));
+                        (lst + m)[h ? pos : 64 + lane] = ent[j];
+                        if constexpr (RECORD) {
+                            const bool hb = h & !(r2 < blo);
+                            const uint64_t bm = __builtin_amdgcn_ballot_w64(hb);
+                            if (bm) {
+                                const int bp = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bm, (uint32_t)nb));
+                                if (hb && bp < kCpBandMax) bnd[bp] = m + pos;
+                                nb += __popcll(bm);
+                            }
+                        } else {
+                            bandacc |= __builtin_amdgcn_ballot_w64(fabsf(r2 - sc.fbcut2) < bw);
+                        }
+                        m += __popcll(hm);
+                    }
+                }
+                return bandacc;
+            };
+            int m, nb;
+            if (sweep(std::false_type{}, m, nb)) {
+                // hits near the build radius: again, noting where they went (rare)
+                __builtin_amdgcn_wave_barrier();
+                sweep(std::true_type{}, m, nb);
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (nb > kCpBandMax) {
+                // rare twice over: k_build builds this target
+                if (lane == 0) lcount[t] = -1;
+                continue;
+            }
+            // the target itself is a hit (r^2 = 0): its list position
+            int sp = -1;
+            for (int b0 = 0; b0 < m && sp < 0; b0 += 64) {
+                const int i = b0 + lane;
+                const uint64_t f = __builtin_amdgcn_ballot_w64(i < m && lst[i] == eself);
+                if (f) sp = b0 + (int)__builtin_ctzll(f);
+            }
+            if (nb == 0) {
+                // the common case: the list without the target, as quads, the
+                // tail of the last quad zeroed
+                m -= sp >= 0 ? 1 : 0;
+                const int mm = min(m, cap);
+                const int q = lane, b = 4 * lane;
+                if (q < ((mm + 3) >> 2)) {
+                    const uint4 s4 = reinterpret_cast<const uint4 *>(lst)[q];
+                    const unsigned s5 = lst[b + 4];
+                    const int d = sp >= 0 ? sp - b : 4;   // entries of this quad before the target
+                    uint4 o;
+                    o.x = d > 0 ? s4.x : s4.y;
+                    o.y = d > 1 ? s4.y : s4.z;
+                    o.z = d > 2 ? s4.z : s4.w;
+                    o.w = d > 3 ? s4.w : s5;
+                    o.x = b < mm ? o.x : 0u;
+                    o.y = b + 1 < mm ? o.y : 0u;
+                    o.z = b + 2 < mm ? o.z : 0u;
+                    o.w = b + 3 < mm ? o.w : 0u;
+                    nlist[(int64_t)q * n + t] = o;
+                }
+            } else {
+                // band hits: exact tests; drop the failures and the target,
+                // keeping the order of the rest (rare)
+                if (nb > kCpBandMax) {
+                    // rare twice over: k_build builds this target
+                    if (lane == 0) lcount[t] = -1;
+                    continue;
+                }
+                bool fail = false;
+                int fpos = 0;
+                if (lane < nb) {
+                    fpos = bnd[lane];
+                    const unsigned e = lst[fpos];
+                    const int s = (int)(e & kSlotMask);
+                    const bool wl = (e & kWallBit) != 0u;
+                    if constexpr (MIXED) {
+                        int qi[3];
+                        V::qpos(V::loadA(rec, t), qi);
+                        double qs[3];
+                        exact_target<DIM>(qi, qs);
+                        const typename V::v4 Aj = wl ? V::wall_A(wpos[s]) : V::loadA(rec, s);
+                        fail = !(exact_r2<DIM>(qs, Aj, e) < sc.qbcut2);
+                    } else {
+                        double pi[3], pj[3], rr[3];
+                        V::pos(V::loadA(rec, t), pi);
+                        if (wl) V::wall_pos(wpos[s], pj);
+                        else V::pos(V::loadA(rec, s), pj);
+                        sub_vec<DIM>(pi, pj, rr);
+                        fail = !(norm2<DIM>(rr) < sc.bcut2);
+                    }
+                }
+                if (lane == nb) {
+                    fpos = sp;
+                    fail = sp >= 0;
+                }
+                const uint64_t dm = __builtin_amdgcn_ballot_w64(fail);
+                if (dm) {
+                    const int nd = __popcll(dm);
+                    for (int b0 = 0; b0 < m; b0 += 64) {
+                        const int i = b0 + lane;
+                        const unsigned v = i < m ? lst[i] : 0u;
+                        int before = 0;
+                        bool gone = false;
+                        for (int f = 0; f <= nb; ++f) {
+                            if (!((dm >> f) & 1ull)) continue;
+                            const int fp = __builtin_amdgcn_readlane(fpos, f);
+                            before += fp < i ? 1 : 0;
+                            gone |= fp == i;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        if (i < m && !gone) lst[i - before] = v;
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                    m -= nd;
+                }
+                const int mm = min(m, cap);
+                const int mq = (mm + 3) & ~3;
+                if (lane < mq - mm) lst[mm + lane] = 0u;
+                __builtin_amdgcn_wave_barrier();
+                if (lane < (mq >> 2)) nlist[(int64_t)lane * n + t] = reinterpret_cast<const uint4 *>(lst)[lane];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                lcount[t] = m;
+                if (m > cap) atomicOr(flags, 4u);
+            }
+        }
+        t0 = t1;
+    }
+}
+
 // Candidate tests and list build alone (kSplitBuild): lists of every target
 // and their lengths (lcount); a list longer than cap raises
 // SPH_FLAG_CAPACITY (its target searches the cells in the sweeps).  SKIN:
 // with radius 2h + skin, on build steps only (*gate != 0).
-template <int DIM, bool MIXED, bool SKIN, int PF>
+template <int DIM, bool MIXED, bool SKIN, int PF, bool FALLBACK>
 __global__ __launch_bounds__(kMaxBlock) void k_build(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     const int *__restrict__ skey, const int *__restrict__ cstart, const int *__restrict__ wstart,
@@ -1005,6 +1312,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_build(
     const Chunk ch = map[blockIdx.x];
     const int k = ch.begin + threadIdx.x;
     if (k >= ch.end) return;
+    // after k_build_cp: only the targets it left (lcount = -1)
+    if constexpr (FALLBACK) {
+        if (lcount[k] != -1) return;
+    }
     const InstDev &I = inst[ch.inst];
     const int lk = skey[k] - I.cell_base;
     const v4 Ai = V::loadA(rec, k);
@@ -1203,10 +1514,26 @@ template <int DIM, bool MIXED, bool SKIN, int PF>
 static void build_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
 {
     using R = Rec<DIM, MIXED>;
-    k_build<DIM, MIXED, SKIN, PF><<<d.nfchunks, d.block, 0, s>>>(
-        sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, static_cast<const typename R::v4 *>(d.rec),
-        static_cast<const typename R::wpos_t *>(d.wpos), static_cast<const typename Cand<DIM>::t *>(d.cpos),
-        static_cast<const typename Cand<DIM>::t *>(d.wcpos), d.nlist, d.lcount, d.list_cap, d.flags, d.gate);
+    using CT = typename Cand<DIM>::t;
+    const auto *rec = static_cast<const typename R::v4 *>(d.rec);
+    const auto *wp = static_cast<const typename R::wpos_t *>(d.wpos);
+    const auto *cp = static_cast<const CT *>(d.cpos);
+    const auto *wcp = static_cast<const CT *>(d.wcpos);
+    const int64_t woff = static_cast<const char *>(d.wcpos) - static_cast<const char *>(d.cpos);
+    const bool cell_pair = kCellPairBuild && sc.key_order == 0 && d.list_cap <= kCpListMax && woff >= 0 &&
+                           woff < (int64_t)UINT32_MAX;
+    if (cell_pair) {
+        k_build_cp<DIM, MIXED, SKIN><<<d.nfchunks, d.block, 0, s>>>(
+            sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, rec, wp, cp, (uint32_t)woff, d.nlist,
+            d.lcount, d.list_cap, d.flags, d.gate);
+        k_build<DIM, MIXED, SKIN, PF, true><<<d.nfchunks, d.block, 0, s>>>(
+            sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, rec, wp, cp, wcp, d.nlist, d.lcount,
+            d.list_cap, d.flags, d.gate);
+    } else {
+        k_build<DIM, MIXED, SKIN, PF, false><<<d.nfchunks, d.block, 0, s>>>(
+            sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, rec, wp, cp, wcp, d.nlist, d.lcount,
+            d.list_cap, d.flags, d.gate);
+    }
 }
 
 template <int DIM, bool MIXED>
