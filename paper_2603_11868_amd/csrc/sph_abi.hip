@@ -90,6 +90,7 @@ struct sph_ctx {
     SimConst sc{};
     std::vector<InstDev> idev;
     std::vector<Chunk> fmap, wmap;
+    std::vector<Chunk> rmap;     // first reduction level over the per-chunk partials
     int64_t N = 0, Nw = 0, C = 0;
     int block = 256;
     int lcap = 96;
@@ -101,7 +102,7 @@ struct sph_ctx {
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
-        o_wkey, o_wskey, o_partials, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
+        o_wkey, o_wskey, o_partials, o_rmap, o_subpart, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
         o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax, o_gate, o_disp, o_xb;
     // state
     bool bound = false, primed = false, cells_built = false;
@@ -211,6 +212,8 @@ void build_layout(sph_ctx *c)
     c->o_wkey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
     c->o_wskey = take(sizeof(int) * std::max<int64_t>(c->Nw, 1));
     c->o_partials = take(sizeof(double) * kNPart * std::max<size_t>(c->fmap.size(), 1));
+    c->o_rmap = take(sizeof(Chunk) * std::max<size_t>(c->rmap.size(), 1));
+    c->o_subpart = take(sizeof(double) * kNPart * std::max<size_t>(c->rmap.size(), 1));
     c->o_fmap = take(sizeof(Chunk) * std::max<size_t>(c->fmap.size(), 1));
     c->o_wmap = take(sizeof(Chunk) * std::max<size_t>(c->wmap.size(), 1));
     c->o_inst = take(sizeof(InstDev) * c->idev.size());
@@ -273,6 +276,17 @@ void build_maps(sph_ctx *c)
     }
     c->fmap = xcd_order(c->fmap);
     c->wmap = xcd_order(c->wmap);
+    // the partial sums of an instance's chunks are reduced in two levels:
+    // fixed runs of kReduceRows chunk rows per block, then the runs (a fixed
+    // order, so the sums do not depend on scheduling)
+    c->rmap.clear();
+    for (size_t b = 0; b < c->inst.size(); ++b) {
+        InstDev &I = c->idev[b];
+        I.sub_begin = (int)c->rmap.size();
+        for (int r = I.chunk_begin; r < I.chunk_end; r += kReduceRows)
+            c->rmap.push_back({(int)b, r, std::min(r + kReduceRows, I.chunk_end), (int)c->rmap.size()});
+        I.sub_end = (int)c->rmap.size();
+    }
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -699,6 +713,9 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.wkey = reinterpret_cast<int *>(ws + c->o_wkey);
     d.wskey = reinterpret_cast<int *>(ws + c->o_wskey);
     d.partials = reinterpret_cast<double *>(ws + c->o_partials);
+    d.rmap = reinterpret_cast<Chunk *>(ws + c->o_rmap);
+    d.subpart = reinterpret_cast<double *>(ws + c->o_subpart);
+    d.nrblocks = (int)c->rmap.size();
     d.fmap = reinterpret_cast<Chunk *>(ws + c->o_fmap);
     d.wmap = reinterpret_cast<Chunk *>(ws + c->o_wmap);
     d.inst = reinterpret_cast<InstDev *>(ws + c->o_inst);
@@ -722,6 +739,8 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
         HIP_TRY(hipMemcpyAsync(d.fmap, c->fmap.data(), sizeof(Chunk) * c->fmap.size(), hipMemcpyHostToDevice, s));
     if (!c->wmap.empty())
         HIP_TRY(hipMemcpyAsync(d.wmap, c->wmap.data(), sizeof(Chunk) * c->wmap.size(), hipMemcpyHostToDevice, s));
+    if (!c->rmap.empty())
+        HIP_TRY(hipMemcpyAsync(d.rmap, c->rmap.data(), sizeof(Chunk) * c->rmap.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d.inst, c->idev.data(), sizeof(InstDev) * c->idev.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fill_i32(d.cnt, c->C + 1, 0, s));
     HIP_TRY(launch_fill_i32(reinterpret_cast<int *>(d.flags), 16, 0, s));

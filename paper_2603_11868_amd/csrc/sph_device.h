@@ -20,6 +20,7 @@
 namespace sphx {
 
 constexpr int kMaxBlock = 256;
+constexpr int kReduceRows = 1024;     // chunk rows per block of the first reduction level
 constexpr int kNPart = 16;            // per-chunk partial sums (see k_final_reduce)
 
 struct __align__(16) dvec2 { double x, y; };
@@ -47,6 +48,7 @@ struct InstDev {
     int fluid_off, n_fluid;
     int wall_off, n_wall;
     int chunk_begin, chunk_end;        // fluid chunks of the instance
+    int sub_begin, sub_end;            // its rows of the first reduction level
     double c0;
 };
 

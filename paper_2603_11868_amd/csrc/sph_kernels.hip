@@ -260,7 +260,7 @@ hipError_t launch_half2(const SimConst &sc, const Dev &d, hipStream_t s, int kic
 // per-instance reductions -> dt, diag
 // ---------------------------------------------------------------------------
 
-constexpr int kReduceBlock = 1024;     // one block per instance: wide, to keep many rows in flight
+constexpr int kReduceBlock = 256;      // second level: one block per instance over its first-level rows
 
 // Verlet skin: called once per instance (thread 0 of its reduction block)
 // with the step dt_n it planned and the max|v|, max|a| the next drift starts
@@ -362,6 +362,33 @@ hipError_t launch_save_build_positions(const SimConst &sc, const Dev &d, hipStre
     return hipGetLastError();
 }
 
+// First level: the chunk rows [begin, end) of one instance, summed (maxima for
+// the max slots) into output row id.
+__global__ __launch_bounds__(256) void k_reduce_rows(const Chunk *__restrict__ rmap,
+                                                     const double *__restrict__ partials,
+                                                     double *__restrict__ subpart)
+{
+    const Chunk rb = rmap[blockIdx.x];
+    constexpr int R = 256 / kNPart;
+    const int q = threadIdx.x % kNPart;
+    const int r0 = threadIdx.x / kNPart;
+    const bool mx = is_max_slot(q);
+    double acc = 0.0;                      // the max slots hold non-negative values
+#pragma unroll 8
+    for (int c = rb.begin + r0; c < rb.end; c += R) {
+        const double x = partials[(int64_t)c * kNPart + q];
+        acc = mx ? fmax(acc, x) : acc + x;
+    }
+    __shared__ double rows[R][kNPart];
+    rows[r0][q] = acc;
+    __syncthreads();
+    if (threadIdx.x < kNPart) {
+        double t = rows[0][q];
+        for (int r = 1; r < R; ++r) t = mx ? fmax(t, rows[r][q]) : t + rows[r][q];
+        subpart[(int64_t)rb.id * kNPart + q] = t;
+    }
+}
+
 __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
     SimConst sc, const InstDev *__restrict__ inst, const double *__restrict__ partials,
     double *__restrict__ dt, double *__restrict__ diag, int *__restrict__ clampc,
@@ -377,8 +404,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
     const int r0 = threadIdx.x / kNPart;
     const bool mx = is_max_slot(q);
     double acc = 0.0;                      // the max slots hold non-negative values
-#pragma unroll 8
-    for (int c = I.chunk_begin + r0; c < I.chunk_end; c += R) {
+    for (int c = I.sub_begin + r0; c < I.sub_end; c += R) {
         const double x = partials[(int64_t)c * kNPart + q];
         acc = mx ? fmax(acc, x) : acc + x;
     }
@@ -438,7 +464,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
 hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s)
 {
     if (sc.n_inst <= 0) return hipSuccess;
-    k_final_reduce<<<sc.n_inst, kReduceBlock, 0, s>>>(sc, d.inst, d.partials, d.dt, d.diag, d.clampc, d.flags, prime,
+    if (d.nrblocks > 0) k_reduce_rows<<<d.nrblocks, 256, 0, s>>>(d.rmap, d.partials, d.subpart);
+    k_final_reduce<<<sc.n_inst, kReduceBlock, 0, s>>>(sc, d.inst, d.subpart, d.dt, d.diag, d.clampc, d.flags, prime,
                                                       d.nsub, d.dtsub, d.nsub_max, d.gate, d.disp);
     return hipGetLastError();
 }

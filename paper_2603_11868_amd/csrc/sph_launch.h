@@ -35,6 +35,9 @@ struct Dev {
     int *wkey, *wskey;        // wall keys (storage, sorted)
     double *scratch;          // reorder gather buffer
     double *partials;         // [nchunks * kNPart]
+    Chunk *rmap;              // first reduction level: block -> (instance, rows of partials, output row)
+    double *subpart;          // [nrblocks * kNPart] its sums
+    int nrblocks;
     Chunk *fmap, *wmap;
     InstDev *inst;
     unsigned *flags;
