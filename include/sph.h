@@ -205,7 +205,9 @@ const char *sph_last_error(void);
  * grid of every instance (origin tank_lo - 3 dx, ceil((tank extent + 6 dx) /
  * (2h + skin)) cells per axis; keys row-major, x fastest, or in tiled Morton
  * order per key_order) and the workspace layout.  No device memory is
- * touched.  On success *out owns a context to be released by sph_destroy. */
+ * touched.  On success *out owns a context to be released by sph_destroy.
+ * (The paper, Sec. 5 "Cell linked-list, direct search and sorting": cells
+ * for the neighbour search; Sec. 6: the dam-break workloads.) */
 sph_status sph_create(const sph_params *p, sph_ctx **out);
 
 /* Release the context and anything the library owns (host objects, graphs,
@@ -225,7 +227,10 @@ sph_status sph_workspace_size(const sph_ctx *ctx, size_t *bytes);
 
 /* Attach caller buffers (all device pointers) and build the static wall cell
  * table: wall keys, the stable sort of walls by cell (wall_perm), wall_start
- * and the sorted wall records.  Synchronises `stream` before returning. */
+ * and the sorted wall records.  Synchronises `stream` before returning.
+ * (Sec. 4 "Implementing SYCL kernels in SPHinXsys": the kernel-shell layer
+ * hands the kernels their data as raw pointers, usable as arrays; here the
+ * caller's raw device arrays.) */
 sph_status sph_bind(sph_ctx *ctx, const sph_buffers *b, void *stream);
 
 /* Bytes of the library-owned workspace behind sph_bind_static (per device). */
@@ -248,31 +253,45 @@ sph_status sph_bind_static(sph_ctx *ctx, const sph_buffers *b, void *stream);
 
 /* Step 0: cell table at the current positions, density with dt = 0 (so
  * rho <- rho_sum + max(0, rho - rho_sum) rho0/rho), forces, reductions.  Gives
- * a^0, dt^0 and diag; resets diag and the step counter. */
+ * a^0, dt^0 and diag; resets diag and the step counter.  (Sec. 4 and 5: the
+ * stages of a step without its first half.) */
 sph_status sph_prime(sph_ctx *ctx, void *stream);
 
 /* Cell keys from the current positions (and the per-cell counts the sort
- * consumes).  Must be followed by sph_sort before the next sph_build_cells. */
+ * consumes).  Must be followed by sph_sort before the next sph_build_cells.
+ * (Sec. 5: the cell linked list built concurrently on the device; the paper
+ * inserts with atomics, here integer counts per cell then a scan, so that the
+ * order inside a cell does not depend on scheduling.) */
 sph_status sph_build_cells(sph_ctx *ctx, void *stream);
 
 /* Stable radix sort of storage indices by key (perm), cell_start, and the
  * sorted sweep records.  reorder != 0 also gathers x, v, rho and id into
- * sorted order (perm becomes the identity, key the sorted keys). */
+ * sorted order (perm becomes the identity, key the sorted keys).  (Sec. 5:
+ * particles sorted on the device with a radix sort rather than a quick sort;
+ * Sec. 6: the re-sort period of the benchmarks.) */
 sph_status sph_sort(sph_ctx *ctx, int32_t reorder, void *stream);
 
-/* Density sweep: rho (storage order), neighbour counts, P.  Uses dt[]. */
+/* Density sweep: rho (storage order), neighbour counts, P.  Uses dt[].
+ * (Sec. 5: direct search, kernel values computed for the particles of the
+ * nearest cells; Sec. 4: a particle_for over the fluid particles.  The
+ * per-target neighbour list it also builds is this library's, see
+ * list_cap.) */
 sph_status sph_density(sph_ctx *ctx, void *stream);
 
-/* Force sweep: a (storage order).  Does not kick. */
+/* Force sweep: a (storage order).  Does not kick.  (Sec. 5: the pairs of
+ * the nearest cells; Sec. 4: a particle_for.) */
 sph_status sph_forces(sph_ctx *ctx, void *stream);
 
 /* half = 1: v += dt/2 a, x += dt v, then cell keys as sph_build_cells.
- * half = 2: v += dt/2 a, then the reductions (dt[], diag[]). */
+ * half = 2: v += dt/2 a, then the reductions (dt[], diag[]).  (Sec. 4: the
+ * per-particle updates are a particle_for, the time step and the diagnostics
+ * a particle_reduce.) */
 sph_status sph_integrate(sph_ctx *ctx, int32_t half, void *stream);
 
 /* n_steps full steps of every instance: half 1 + keys, sort (with the reorder
  * on steps where steps_done % K == 0), density, force fused with half 2,
- * reductions.  dt stays on the device; asynchronous.
+ * reductions.  dt stays on the device; asynchronous.  (Sec. 4 and 5 for the
+ * stages; the instances batched into the same launches are this library's.)
  *
  * With SPH_SCHEME_DUAL a step is one advection step of every instance, and
  * each advection step reads the largest planned sub-step count back to the
