@@ -227,16 +227,18 @@ def load_valu(workload, precision, kernel):
 
 
 def run_gpu(case, precision, steps, warmup, graph, timing, reorder_every=None, block=0,
-            list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph", skin_h=0.0, key_order="row"):
+            list_cap=0, prefetch=0, stage_steps=0, scheme="wcsph", skin_h=0.0, key_order="row",
+            tuned=True, build=None):
     """One timed leg: prime, `warmup` untimed steps, `steps` timed steps, then
-    optionally `stage_steps` eager steps with events around every stage."""
+    optionally `stage_steps` eager steps with events around every stage.
+    tuned: launch parameters left unset come from the autotuner's cache."""
     import torch
     from paper_2603_11868_amd import sph
 
     sim = sph.Simulation(case, precision=precision, reorder_every=reorder_every,
                          use_graph=graph, block_threads=block,
                          list_cap=list_cap, prefetch=prefetch, scheme=scheme,
-                         skin=skin_h * case.h, key_order=key_order)
+                         skin=skin_h * case.h, key_order=key_order, tuned=tuned, build=build)
     sim.key_order = key_order
     sim.prime()
     sim.step(warmup)
@@ -459,6 +461,11 @@ def main(argv=None):
                          "run is the reference of the error statement)")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--build", type=int, default=None, choices=(0, 1, 2),
+                    help="list build: 1 lane per target, 2 cell pairs, 0 the library's default "
+                         "(default: tuned, else 0)")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="ignore the autotuner's cache for launch parameters left unset")
     ap.add_argument("--list", type=int, default=0, help="neighbour-list capacity (-1: no list)")
     ap.add_argument("--prefetch", type=int, default=0, help="candidate records in flight (4 or 8)")
     ap.add_argument("--reorder-every", type=int, default=None)
@@ -504,7 +511,7 @@ def main(argv=None):
 
     common = dict(reorder_every=args.reorder_every, block=args.block, list_cap=args.list,
                   prefetch=args.prefetch, scheme=args.scheme, key_order=args.key_order,
-                  stage_steps=min(args.steps, 50))
+                  stage_steps=min(args.steps, 50), tuned=not args.no_tuned, build=args.build)
     sim, h, secs, stages, flags = run_gpu(case, args.precision, args.steps, args.warmup,
                                           args.graph, timing=not args.graph,
                                           skin_h=args.skin, **common)
@@ -520,6 +527,9 @@ def main(argv=None):
     cons = drift(case, sim.info.mass, sim.diag0, sim.diag1)
     state_head = {"x": h["x"], "v": h["v"], "rho": h["rho"], "id": h["id"]}
     mass = float(sim.info.mass)
+    tuned_params = sim.tuned
+    launch = {"block_threads": int(sim.params.block_threads) or 256, "build": int(sim.params.build),
+              "prefetch": int(sim.params.prefetch) or 8}
     timed_builds = sim.timed_builds
     sweeps_timed = sim.sweeps_timed
     sim_time = cons["sim_time_s"]
@@ -616,9 +626,8 @@ def main(argv=None):
         "config": {"workload": WORKLOADS[args.case], "case": args.case,
                    "precision": args.precision, "n_fluid": n_fluid, "n_wall": case.n_wall,
                    "reorder_every": case.reorder_every if args.reorder_every is None else args.reorder_every,
-                   "graph": bool(args.graph), "block_threads": args.block or 256,
-                   "list_cap": args.list,
-                   "prefetch": args.prefetch or 8, "scheme": args.scheme,
+                   "graph": bool(args.graph), **launch, "tuned": tuned_params,
+                   "list_cap": args.list, "scheme": args.scheme,
                    "skin_h": args.skin, "key_order": args.key_order},
         "roofline": roof, "hbm": hbm, "cpu_baseline": cpu, "stage_us": stage_us,
         "compare": other, "skin_leg": skin_leg, "flags": int(flags), **extra,

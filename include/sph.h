@@ -155,7 +155,14 @@ typedef struct {
                                 2h + skin, both reused by sph_step_batched
                                 until the particles may have moved skin / 2
                                 (below) */
-    int32_t reserved[2];
+    int32_t build;           /* neighbour-list build: 0 = default (cell pairs
+                                in 3D, one lane per target in 2D), 1 = one
+                                lane per target, 2 = cell pairs (the sources of
+                                a cell's stencil held by the lanes of a wave,
+                                the cell's targets taken one at a time;
+                                row-major keys and list_cap <= 255, else one
+                                lane per target).  All give the same lists */
+    int32_t reserved;
 } sph_params;
 
 typedef struct {

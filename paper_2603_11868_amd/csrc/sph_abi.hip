@@ -516,6 +516,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     lcap = (lcap + 3) & ~3;   // stored in quads
     const int pref = p->prefetch == 0 ? 8 : p->prefetch;
     if (pref != 4 && pref != 8) return fail(SPH_E_ARG, "prefetch must be 0, 4 or 8");
+    if (p->build < 0 || p->build > 2) return fail(SPH_E_ARG, "build must be 0, 1 or 2");
     if (lcap > 4096) return fail(SPH_E_ARG, "list_cap must be at most 4096");
     if (p->scheme != SPH_SCHEME_WCSPH && p->scheme != SPH_SCHEME_DUAL) return fail(SPH_E_ARG, "unknown scheme");
     if (p->key_order != SPH_KEYS_ROW_MAJOR && p->key_order != SPH_KEYS_MORTON_TILES)
@@ -726,6 +727,9 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.block = c->block;
     d.list_cap = c->lcap;
     d.prefetch = c->pref;
+    // cell pairs pay in 3D (about 18 targets per cell); in 2D (about 7) the
+    // per-cell set-up outweighs them
+    d.cell_pair = c->p.build == 2 || (c->p.build == 0 && c->p.dim == 3);
     d.nlist = reinterpret_cast<uint4 *>(ws + c->o_nlist);
     d.lcount = reinterpret_cast<int *>(ws + c->o_lcount);
     d.drho = reinterpret_cast<double *>(ws + c->o_drho);

@@ -48,6 +48,7 @@ struct Dev {
     int *lcount;              // [N] hits per sorted target (may exceed list_cap)
     int list_cap;             // 0: sweeps traverse the stencil (no list)
     int prefetch;             // candidate records in flight per thread (4 or 8)
+    bool cell_pair;           // list build as cell pairs where it applies
     // dual scheme
     double *drho;             // [N] continuity rate of the last density relaxation
     int *nsub;                // [B] acoustic sub-steps of the next advection step

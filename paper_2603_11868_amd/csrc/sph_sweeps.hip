@@ -37,8 +37,6 @@ constexpr bool kSkinSplitWalk = true;
 // density walk after it: the build then runs at the occupancy of its own
 // registers, not at that of the FP64 density sums.
 constexpr bool kSplitBuild = true;
-// The split build as cell pairs (k_build_cp; row-major keys).
-constexpr bool kCellPairBuild = true;
 // List walks gather records cooperatively (walk_coop).
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
@@ -1520,7 +1518,7 @@ static void build_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
     const auto *cp = static_cast<const CT *>(d.cpos);
     const auto *wcp = static_cast<const CT *>(d.wcpos);
     const int64_t woff = static_cast<const char *>(d.wcpos) - static_cast<const char *>(d.cpos);
-    const bool cell_pair = kCellPairBuild && sc.key_order == 0 && d.list_cap <= kCpListMax && woff >= 0 &&
+    const bool cell_pair = d.cell_pair && sc.key_order == 0 && d.list_cap <= kCpListMax && woff >= 0 &&
                            woff < (int64_t)UINT32_MAX;
     if (cell_pair) {
         k_build_cp<DIM, MIXED, SKIN><<<d.nfchunks, d.block, 0, s>>>(

@@ -67,7 +67,7 @@ class sph_params(C.Structure):
                 ("use_graph", C.c_int32), ("list_cap", C.c_int32),
                 ("prefetch", C.c_int32), ("scheme", C.c_int32), ("key_order", C.c_int32),
                 ("cfl_adv", C.c_double), ("eta", C.c_double), ("skin", C.c_double),
-                ("reserved", C.c_int32 * 2)]
+                ("build", C.c_int32), ("reserved", C.c_int32)]
 
 
 class sph_buffers(C.Structure):
@@ -269,10 +269,28 @@ class Simulation:
     def __init__(self, case, precision="fp64", reorder_every=None, block_threads=0,
                  use_graph=False, device="cuda", alpha=None, g=None,
                  cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0,
-                 scheme="wcsph", skin=0.0, key_order="row", static_scratch=False):
+                 scheme="wcsph", skin=0.0, key_order="row", static_scratch=False, build=None,
+                 tuned=False):
         import torch
         self.torch = torch
         self.case = case
+        self.tuned = None
+        if tuned:
+            # launch parameters from the autotuner's cache for this workload
+            # (block size, list build, candidate prefetch), where present
+            from . import tune as _tune
+            best = _tune.lookup(case, precision)
+            if best:
+                # only the parameters the caller left unset
+                self.tuned = {k: best[k] for k in ("block_threads", "build", "prefetch") if k in best}
+                if not block_threads:
+                    block_threads = self.tuned.get("block_threads", 0)
+                if build is None:
+                    build = self.tuned.get("build", 0)
+                if not prefetch:
+                    prefetch = self.tuned.get("prefetch", 0)
+        if build is None:
+            build = 0
         self.dim = dim = case.dim
         self.device = torch.device(device)
         B = len(case.instances)
@@ -303,6 +321,7 @@ class Simulation:
         p.use_graph = int(bool(use_graph))
         p.list_cap = int(list_cap)
         p.prefetch = int(prefetch)
+        p.build = int(build)
         p.skin = float(skin)               # Verlet skin, a length (0: none)
         p.key_order = {"row": SPH_KEYS_ROW_MAJOR, "morton": SPH_KEYS_MORTON_TILES}[key_order]
         if scheme == "dual":
