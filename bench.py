@@ -38,14 +38,14 @@ METRIC = "M particle-updates/s (3D WCSPH step) + achieved HBM GB/s vs FP64 path"
 FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
 FP32_VALU_PEAK_TFLOPS = 157.3    # MI355X FP32 vector, packed (twice the unpacked rate)
 HBM_PEAK_GBS = 8000.0
-SWEEP_STAGES = ("density", "force", "sub_pressure", "sub_density")
+SWEEP_STAGES = ("build", "density", "force", "sub_pressure", "sub_density")
 CLOCK_HZ, N_CU = 2.4e9, 256
 
-# FP64 flops per candidate test and per neighbour pair (viscosity excluded:
-# it runs on approaching pairs only, so leaving it out keeps the count a
-# lower bound).  Candidate: r = x_i - x_j, r^2.  Density pair: sqrt, q, t,
-# t^3, W, F, v_ij.r, two accumulations.  Force pair: sqrt, q, t, t^3, F,
-# v_ij.r, (P_i + P_j) F, two vector accumulations.
+# Flops per candidate test and per neighbour pair (viscosity excluded: it
+# runs on approaching pairs only, so leaving it out keeps the count a lower
+# bound).  Candidate (list build, FP32 on both paths): r = x_i - x_j, r^2.
+# Density pair: sqrt, q, t, t^3, W, F, v_ij.r, two accumulations.  Force
+# pair: sqrt, q, t, t^3, F, v_ij.r, (P_i + P_j) F, two vector accumulations.
 FLOPS = {
     2: {"cand": 5, "density": 20, "force": 24},
     3: {"cand": 8, "density": 23, "force": 30},
@@ -410,19 +410,23 @@ def roofline(args, case, sim, h, stages, precision, skin_h):
                 "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
                 "traffic": load_traffic(args.case, key, name),
                 "flops_per_launch": float(flops), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
-    elif name in ("density", "force"):
-        flops = FLOPS[dim][name] * pairs
+    elif name in ("build", "density", "force"):
         cands = 0
-        if name == "density":
-            # the candidate tests run in the density sweep of a build step
-            # only (every step without a skin); the force sweep walks the list
+        if name == "build":
+            # the candidate tests of the list build, on build steps only
+            # (every step without a skin); the sweeps walk the lists
             cands = candidate_count(sim, h)
-            flops += FLOPS[dim]["cand"] * cands * (sim.timed_builds / args.steps)
+            flops = FLOPS[dim]["cand"] * cands * (sim.timed_builds / args.steps)
+        else:
+            flops = FLOPS[dim][name] * pairs
         achieved = flops / avg_s / 1e12
         traffic = load_traffic(args.case, key, name)
+        if name == "build":
+            # the candidate tests are FP32 arithmetic on both paths
+            peak = FP32_VALU_PEAK_TFLOPS
         roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "peak_kind": "FP64 vector" if precision == "fp64" else "FP32 vector (packed)",
+                "peak_kind": "FP32 vector (packed)" if peak == FP32_VALU_PEAK_TFLOPS else "FP64 vector",
                 "traffic": traffic, "flops_per_launch": float(flops),
                 "candidates": int(cands), "pairs": float(pairs), "avg_ms": round(avg_s * 1e3, 4)}
         if traffic:

@@ -31,10 +31,11 @@ sph_status fail(sph_status st, const std::string &msg)
     } while (0)
 
 enum Stage { ST_KEYS = 0, ST_SCAN, ST_SORT, ST_REORDER, ST_PACK, ST_DENSITY, ST_FORCE, ST_REDUCE,
-             ST_SUB_FIRST, ST_SUB_PRESSURE, ST_SUB_SECOND, ST_SUB_DENSITY, ST_COUNT };
+             ST_SUB_FIRST, ST_SUB_PRESSURE, ST_SUB_SECOND, ST_SUB_DENSITY, ST_BUILD, ST_COUNT };
 const char *kStageNames[ST_COUNT] = {"keys", "cell_scan", "radix_sort", "reorder",
                                      "pack", "density", "force", "reduce",
-                                     "sub_first_half", "sub_pressure", "sub_second_half", "sub_density"};
+                                     "sub_first_half", "sub_pressure", "sub_second_half", "sub_density",
+                                     "build"};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -336,6 +337,10 @@ sph_status do_sort(sph_ctx *c, bool reorder, hipStream_t s, bool timed, int kick
 
 sph_status do_density(sph_ctx *c, int use_dt, hipStream_t s, bool timed)
 {
+    {
+        StageTimer t(c, ST_BUILD, s, timed);
+        TRY(check_launch(launch_build(c->sc, c->dev, c->mixed, s), "build"));
+    }
     StageTimer t(c, ST_DENSITY, s, timed);
     c->list_valid = c->lcap > 0;
     return check_launch(launch_density(c->sc, c->dev, c->mixed, use_dt, s), "density");

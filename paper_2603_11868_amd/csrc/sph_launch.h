@@ -83,6 +83,9 @@ hipError_t launch_pack(const SimConst &sc, const Dev &d, int mixed, hipStream_t 
 // Density sweep (sph_sweeps.hip).  use_dt = 0 for the prime (dt = 0).  With
 // list_cap > 0 it also writes the per-step neighbour list.
 hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s);
+// Candidate tests and neighbour lists (before launch_density, which then
+// walks them); with a skin only on build steps.
+hipError_t launch_build(const SimConst &sc, const Dev &d, int mixed, hipStream_t s);
 // Force sweep.  fused != 0: also v += dt/2 a and all per-chunk partials.
 // list != 0: walk the neighbour list written by this step's density sweep.
 hipError_t launch_force(const SimConst &sc, const Dev &d, int mixed, int fused, int list, hipStream_t s);

@@ -1535,19 +1535,33 @@ static void build_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
 }
 
 template <int DIM, bool MIXED>
+static void build_variant(const SimConst &sc, const Dev &d, hipStream_t s)
+{
+    if (d.gate) {
+        if (d.prefetch == 4) build_dispatch<DIM, MIXED, true, 4>(sc, d, s);
+        else build_dispatch<DIM, MIXED, true, 8>(sc, d, s);
+    } else {
+        if (d.prefetch == 4) build_dispatch<DIM, MIXED, false, 4>(sc, d, s);
+        else build_dispatch<DIM, MIXED, false, 8>(sc, d, s);
+    }
+}
+
+hipError_t launch_build(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
+{
+    if (d.nfchunks <= 0 || d.list_cap <= 0 || !kSplitBuild) return hipSuccess;
+    if (sc.dim == 2) { if (mixed) build_variant<2, true>(sc, d, s); else build_variant<2, false>(sc, d, s); }
+    else { if (mixed) build_variant<3, true>(sc, d, s); else build_variant<3, false>(sc, d, s); }
+    return hipGetLastError();
+}
+
+template <int DIM, bool MIXED>
 static void density_variant(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
 {
     if (d.list_cap <= 0) density_dispatch<DIM, MIXED, 0, 4>(sc, d, use_dt, s);
     else if (kSplitBuild) {
-        if (d.gate) {
-            if (d.prefetch == 4) build_dispatch<DIM, MIXED, true, 4>(sc, d, s);
-            else build_dispatch<DIM, MIXED, true, 8>(sc, d, s);
-            density_dispatch<DIM, MIXED, 3, 4>(sc, d, use_dt, s);
-        } else {
-            if (d.prefetch == 4) build_dispatch<DIM, MIXED, false, 4>(sc, d, s);
-            else build_dispatch<DIM, MIXED, false, 8>(sc, d, s);
-            density_dispatch<DIM, MIXED, 5, 4>(sc, d, use_dt, s);
-        }
+        // the lists come from launch_build
+        if (d.gate) density_dispatch<DIM, MIXED, 3, 4>(sc, d, use_dt, s);
+        else density_dispatch<DIM, MIXED, 5, 4>(sc, d, use_dt, s);
     } else if (d.gate) {
         if (d.prefetch == 4) density_dispatch<DIM, MIXED, 2, 4>(sc, d, use_dt, s);
         else density_dispatch<DIM, MIXED, 2, 8>(sc, d, use_dt, s);
