@@ -207,9 +207,10 @@ def load_l1(workload, precision, kernel):
     return acc if hsh == kernel_source_hash() else None
 
 
-def load_valu(workload, precision, kernel):
-    """VALU instructions (wave64) per launch of a sweep from a committed
-    rocprofv3 summary taken on the current kernel sources (else None)."""
+def load_valu(workload, precision, kernel, unit="valu"):
+    """VALU (or, with unit="salu", SALU) instructions (wave64) per launch of a
+    sweep or the list build from a committed rocprofv3 summary taken on the
+    current kernel sources (else None)."""
     import re
     path = os.path.join(ROOT, "profiles", f"valu_{workload}_{precision}_sq.md")
     if not os.path.exists(path):
@@ -217,7 +218,7 @@ def load_valu(workload, precision, kernel):
     val, hsh = None, None
     with open(path) as f:
         for line in f:
-            m = re.match(r"^- (\w+) valu_insts_per_launch: ([0-9.e+-]+)", line)
+            m = re.match(r"^- (\w+) " + unit + r"_insts_per_launch: ([0-9.e+-]+)", line)
             if m and m.group(1) == kernel:
                 val = float(m.group(2))
             m = re.match(r"^- source_hash: `([0-9a-f]+)`", line)
@@ -367,25 +368,32 @@ def state_errors(case, mass, test, ref):
 
 
 def cpu_baseline(case, nsteps, scheme="wcsph"):
-    """The CPU reference on the same workload: M updates/s over nsteps steps
-    (dual scheme: advection steps, counted in acoustic sub-steps)."""
+    """The CPU reference on the same workload: M updates/s over nsteps steps of
+    every instance of the case, one after the other (dual scheme: advection
+    steps, counted in acoustic sub-steps).  Returns the rate, the threads it
+    used, the seconds timed and the particle updates counted."""
     from oracle import oracle as O
 
-    ref = O.OracleSim.from_case(case)
-    if scheme == "dual":
-        ref.dual_prime()
-        t0 = time.perf_counter()
-        subs = 0
-        for _ in range(nsteps):
-            subs += ref.dual_plan()[1]
-            ref.dual_step(1)
-        t1 = time.perf_counter()
-        return ref, case.n_fluid * subs / (t1 - t0) / 1e6, O.num_threads(), t1 - t0
-    ref.prime()
-    t0 = time.perf_counter()
-    ref.step(nsteps)
-    t1 = time.perf_counter()
-    return ref, case.n_fluid * nsteps / (t1 - t0) / 1e6, O.num_threads(), t1 - t0
+    secs, updates = 0.0, 0
+    for b, inst in enumerate(case.instances):
+        ref = O.OracleSim.from_case(case, index=b)
+        if scheme == "dual":
+            ref.dual_prime()
+            t0 = time.perf_counter()
+            subs = 0
+            for _ in range(nsteps):
+                subs += ref.dual_plan()[1]
+                ref.dual_step(1)
+            secs += time.perf_counter() - t0
+            updates += inst.n_fluid * subs
+        else:
+            ref.prime()
+            t0 = time.perf_counter()
+            ref.step(nsteps)
+            secs += time.perf_counter() - t0
+            updates += inst.n_fluid * nsteps
+        del ref
+    return updates / secs / 1e6, O.num_threads(), secs, updates
 
 
 def roofline(args, case, sim, h, stages, precision, skin_h):
@@ -442,11 +450,12 @@ def roofline(args, case, sim, h, stages, precision, skin_h):
         per = acc / (avg_s * CLOCK_HZ * N_CU)
         roof["l1"] = {"accesses_per_launch": acc, "per_clock_per_cu": round(per, 3),
                       "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
-    vi = load_valu(args.case, key, name)
-    if vi:
-        per = vi / (avg_s * CLOCK_HZ * N_CU)
-        roof["valu_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
-                              "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
+    for unit in ("valu", "salu"):
+        vi = load_valu(args.case, key, name, unit)
+        if vi:
+            per = vi / (avg_s * CLOCK_HZ * N_CU)
+            roof[unit + "_issue"] = {"insts_per_launch": vi, "per_clock_per_cu": round(per, 3),
+                                     "ceiling_per_clock_per_cu": 1.0, "frac": round(per, 3)}
     return roof
 
 
@@ -597,12 +606,13 @@ def main(argv=None):
         cpu_steps = max(1, int(round(5e7 / max(n_fluid, 1))))
         cpu_steps = min(cpu_steps, 100)
     if cpu_steps > 0:
-        _, cv, cores, csecs = cpu_baseline(case, cpu_steps, args.scheme)
+        cv, cores, csecs, cupd = cpu_baseline(case, cpu_steps, args.scheme)
         what = "advection steps (their acoustic sub-steps counted)" if args.scheme == "dual" else "full steps"
         cpu = {"value": round(cv, 4), "unit": "M particle-updates/s", "cores": cores,
                "kind": "oracle",
                "sample": f"{args.case}: FP64 CPU reference, {cpu_steps} {what} after the prime, "
-                         f"all {n_fluid} fluid particles ({csecs:.1f} s timed)"}
+                         f"every instance, all {n_fluid} fluid particles ({cupd} particle updates, "
+                         f"{csecs:.1f} s timed)"}
         log(f"cpu oracle: {cv:.3f} M updates/s on {cores} threads ({csecs:.1f} s)")
 
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
