@@ -211,6 +211,16 @@ __device__ __forceinline__ auto walk_cut2(const SimConst &sc)
     else return sc.cut2;
 }
 
+// Whether a density walk skips list entries at r^2 >= cut2 itself.  A list
+// holds every pair its build found closer than the build radius with an FP32
+// test and a margin of 1e-4 in r^2 -- a superset of the pairs -- so every walk
+// decides each entry: the FP64 walks with r^2 < (2h)^2 in FP64, the forces
+// with the r^2 of their own precision, and the mixed density sweep with the
+// exact fixed-point test inside its pair function (with a skin, the FP32 test
+// of the walk first skips the entries well beyond 2h).
+template <bool MIXED, int LIST>
+constexpr bool density_chk() { return !MIXED || LIST == 2 || LIST == 3; }
+
 // How much of B a sweep needs from each fluid source.
 enum { NEED_NONE = 0, NEED_VEL = 1, NEED_ALL = 2 };
 
@@ -630,18 +640,16 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
 //
 // Candidates are read as FP32 offsets from their cell's origin (the cpos and
 // wcpos copies), U per lane in flight, with the index clamped instead of
-// branched.  A candidate is decided in FP32 except inside a band of relative
-// width 1e-4 around (2h + skin)^2 -- the FP32 r^2 of a pair near the cutoff is
-// within ~3e-6 of the exact one -- where r^2 is recomputed from the records:
-// in FP64 on the FP64 path, so its neighbour set is the exact FP64 one, and
-// from the fixed-point offsets on the mixed path (exact_r2).  On the FP64
-// path a target far outside its cell (a clamped particle) takes the FP64 test
-// for every candidate.  Hits enter a four-entry shift register that is stored
-// as one quad whenever it fills.
+// branched.  A candidate is a hit when its FP32 r^2 is below the build radius
+// (2h + skin)^2 times (1 + 1e-4); the FP32 r^2 of a pair is within ~1e-5 of
+// the exact one, so the list holds every pair closer than the build radius
+// and a few just beyond it, which the walks skip with their own exact test.
+// On the FP64 path a target far outside its cell (a clamped particle) takes
+// the FP64 test for every candidate.  Hits enter a four-entry shift register
+// that is stored as one quad whenever it fills.
 template <int DIM, bool MIXED, int U>
 __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, int lk, int k,
-                                          const typename RV<DIM, MIXED>::real *pi, const double *qs,
-                                          const float *ci,
+                                          const typename RV<DIM, MIXED>::real *pi, const float *ci,
                                           const int *__restrict__ cstart, const int *__restrict__ wstart,
                                           const typename RV<DIM, MIXED>::v4 *__restrict__ rec,
                                           const typename RV<DIM, MIXED>::wpos_t *__restrict__ wpos,
@@ -666,12 +674,11 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
     } else {
         target_offsets<DIM, MIXED>(sc, I, c, pi, o);
     }
-    float lo = fcut2 * (1.0f - 1e-4f), hi = fcut2 * (1.0f + 1e-4f);
+    const float hi = fcut2 * (1.0f + 1e-4f);
+    bool far = false;
     if constexpr (!MIXED) {
-        bool far = false;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) far |= fabs((double)o[a]) > 4.0 * sc.cs;
-        if (far) { lo = -1.0f; hi = __builtin_huge_valf(); }
     }
     int m = 0;
     uint4 buf = make_uint4(0u, 0u, 0u, 0u);
@@ -718,19 +725,14 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
                         bool hit = s < s1 && !(pass == 0 && s == k);
                         if constexpr (MIXED) {
                             hit = hit && r2f < hi;
-                            if (hit && !(r2f < lo)) {
-                                const typename V::v4 Aj = pass == 0 ? V::loadA(rec, s) : V::wall_A(wpos[s]);
-                                hit = exact_r2<DIM>(qs, Aj, rf.bits(s)) < sc.qbcut2;
-                            }
-                        } else {
+                        } else if (!far) {
                             hit = hit && r2f < hi;
-                            if (hit && !(r2f < lo)) {
-                                real pj[3], rr[3];
-                                if (pass == 0) V::pos(V::loadA(rec, s), pj);
-                                else V::wall_pos(wpos[s], pj);
-                                sub_vec<DIM>(pi, pj, rr);
-                                hit = norm2<DIM>(rr) < (real)sc.bcut2;
-                            }
+                        } else if (hit) {
+                            real pj[3], rr[3];
+                            if (pass == 0) V::pos(V::loadA(rec, s), pj);
+                            else V::wall_pos(wpos[s], pj);
+                            sub_vec<DIM>(pi, pj, rr);
+                            hit = norm2<DIM>(rr) < (real)sc.bcut2;
                         }
                         if (hit) {
                             unsigned e = wall_bit | (unsigned)s;
@@ -764,7 +766,8 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
 // Phase 2: fn(wall, s, r, r2, A_j, B_j, e) for the first m (<= cap) entries
 // of target k; the records of U entries (U = 1, 2, 4, 8 or 16; above 4 a
 // round reads U / 4 quads) are fetched before any of them is used.
-// CHK: the list was built with a skin, so entries with r^2 >= cut2 are skipped.
+// CHK: entries with r^2 >= cut2 are skipped (the list is a superset of the
+// pairs: built with a margin, or with a skin).
 template <int DIM, bool MIXED, int U, int NEED, bool CHK = false, class Fn>
 __device__ __forceinline__ void walk_list(const SimConst &sc, int k, int m,
                                           const typename RV<DIM, MIXED>::real *pi,
@@ -990,27 +993,30 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
 // a wave owns 64 consecutive targets (sorted slots) and walks them cell by
 // cell.  For one cell, the sources of its 3^d stencil -- rows in z, y order,
 // per row the fluid slots of its three cells, then their wall slots, the
-// order of the direct search -- form one sequence, of which lane l of
-// register chunk j holds element 64 j + l: its FP32 cell offset shifted into
-// the frame of the target cell, and its list entry.  Each target of the cell
-// (wave-uniform, so its offsets are scalar operands) then tests a chunk with
-// one compare per lane; the hits append to the target's list in lane, that is
-// slot, order through a ballot and mbcnt, into a staging area in LDS that is
-// written out as quads when the target is done.  Every candidate test costs
-// about a dozen VALU instructions per 64 pairs, where a lane per target costs
-// about two dozen per pair; source loads happen once per cell, not once per
-// target.  The decisions are those of build_list (FP32 test, exact recheck in
-// the band around (2h + skin)^2), so the lists are identical.
+// order of the direct search -- form one sequence of S sources held in the
+// first nch = ceil(S / 64) of CH register chunks: lane l of chunk j holds
+// element 64 j + l, as its FP32 position p relative to the centre of the
+// target cell, scaled by -2, its |p|^2, and its list entry.  A target t
+// of the cell (wave-uniform, so its position is a scalar operand) then tests a
+// chunk with three FMAs and a compare, |p|^2 - 2 t.p < R^2 (1 + 1e-4) - |t|^2
+// with R the build radius 2h + skin (positions within 1.5 cells of the
+// centre: the rounding stays below 1e-5 R^2), and one compare against its
+// own entry; the hits append to the target's list in sequence (slot) order
+// through a ballot and mbcnt, into a staging area in LDS written out as
+// quads when the target is done.  The loop over a cell's targets exists in
+// one fully unrolled copy per chunk count (the fewest counts share one copy,
+// whose surplus chunks never hit), chosen once per cell, so the chunk tests
+// carry no branches.  Source loads happen once per cell, not once per target.  The list is the superset of build_list's kind (every pair
+// closer than R, and a few within the margin beyond it, which the walks skip).
 //
-// Cells whose stencil holds more than cp_chunks() * 64 sources mark their
-// targets (lcount = -1) for k_build, which follows with FALLBACK = true and
-// builds only those; tiled Morton keys (stencil rows not contiguous) and
-// capacities above kCpListMax use k_build alone.
+// Cells whose stencil holds more than CH * 64 sources, and targets far
+// outside their cell, are marked (lcount = -1) for k_build, which follows
+// with FALLBACK = true and builds only those; tiled Morton keys (stencil rows
+// not contiguous) and capacities above kCpListMax use k_build alone.
 // ---------------------------------------------------------------------------
 
 template <int DIM> constexpr int cp_chunks() { return DIM == 3 ? 10 : 4; }   // register chunks of 64 sources
 constexpr int kCpListMax = 255;        // list capacity the cell-pair build supports
-constexpr int kCpBandMax = 63;         // band hits of one target awaiting the exact test
 
 // Value of `v` on lane `src` (lane-varying source lane).
 __device__ __forceinline__ int lane_value(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
@@ -1019,12 +1025,10 @@ template <int DIM, bool MIXED, bool SKIN>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_build_cp(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     const int *__restrict__ skey, const int *__restrict__ cstart, const int *__restrict__ wstart,
-    const typename Rec<DIM, MIXED>::v4 *__restrict__ rec, const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos,
     const typename Cand<DIM>::t *__restrict__ cpos, uint32_t wcpos_off,
     uint4 *__restrict__ nlist, int *__restrict__ lcount, int cap, unsigned *__restrict__ flags,
     const int *__restrict__ gate)
 {
-    using V = RV<DIM, MIXED>;
     using CT = typename Cand<DIM>::t;
     constexpr int NR = DIM == 3 ? 18 : 6;                 // (row, kind) ranges of a stencil
     if constexpr (SKIN) {
@@ -1034,8 +1038,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     // staging: a whole stencil of hits, and room past it for the writes of
     // the lanes without a hit
     constexpr int kCpStage = CH * 64;
+    static_assert(((kCpListMax + 3) & ~3) <= kCpStage + 64, "the quads of a full list stay inside the staging");
     __shared__ __align__(16) unsigned stage[kMaxBlock / 64][kCpStage + 128];
-    __shared__ int bands[kMaxBlock / 64][kCpBandMax + 1];
     const Chunk ch = map[blockIdx.x];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1043,12 +1047,10 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     const int w1 = min(w0 + 64, ch.end);
     if (w0 >= w1) return;                                 // the whole wave
     unsigned *lst = stage[wv];
-    int *bnd = bands[wv];
     const InstDev &I = inst[ch.inst];
     const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
-    const float fcs = sc.fcs;
-    const float blo = sc.fbcut2 * (1.0f - 1e-4f), bhi = sc.fbcut2 * (1.0f + 1e-4f);
-    const float bw = sc.fbcut2 * 1e-4f;                   // half width of that band
+    const float fcs = sc.fcs, hcs = 0.5f * sc.fcs;
+    const float bhi = sc.fbcut2 * (1.0f + 1e-4f);        // the build radius^2 with its margin
     const char *cbase = reinterpret_cast<const char *>(cpos);
     const int n = sc.N;
     int t0 = w0;
@@ -1087,13 +1089,14 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
             t0 = t1;
             continue;
         }
-        // the chunks: source positions in the frame of the target cell, and entries
-        float px[CH], py[CH], pz[CH];
+        // the chunks: -2 p, |p|^2 and the entry of every source
+        float qx[CH], qy[CH], qz[CH], pp[CH];
         unsigned ent[CH];
         int rc = 0;                                       // ranges ending at or before 64 j
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            px[j] = py[j] = pz[j] = 3.0e38f;
+            qx[j] = qy[j] = qz[j] = 0.0f;
+            pp[j] = 3.0e38f;                              // no hit
             ent[j] = 0u;
             if (j < nch) {
                 const int g = 64 * j + lane;
@@ -1115,174 +1118,84 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
                 const uint32_t off = valid ? (wall ? wcpos_off : 0u) + (uint32_t)slot * (uint32_t)sizeof(CT) : 0u;
                 const CT c = *reinterpret_cast<const CT *>(cbase + off);
                 if (valid) {
-                    px[j] = fmaf((float)ox, fcs, c.x);
-                    py[j] = fmaf((float)oy, fcs, c.y);
-                    if constexpr (DIM == 3) pz[j] = fmaf((float)oz, fcs, c.z);
-                    else pz[j] = 0.0f;
+                    // the candidate copies hold offsets from the cell's origin
+                    const float sx = fmaf((float)ox - 0.5f, fcs, c.x);
+                    const float sy = fmaf((float)oy - 0.5f, fcs, c.y);
+                    float sz = 0.0f;
+                    if constexpr (DIM == 3) sz = fmaf((float)oz - 0.5f, fcs, c.z);
+                    qx[j] = -2.0f * sx;
+                    qy[j] = -2.0f * sy;
+                    qz[j] = -2.0f * sz;
+                    pp[j] = sx * sx + sy * sy + sz * sz;
                     ent[j] = (wall ? kWallBit : 0u) | (unsigned)slot | (MIXED ? offset_bits(ox, oy, oz) : 0u);
                 }
             }
         }
-        for (int t = t0; t < t1; ++t) {
-            const CT ot = cpos[t];
-            const float ox_t = ot.x, oy_t = ot.y;
-            float oz_t = 0.0f;
-            if constexpr (DIM == 3) oz_t = ot.z;
-            // a target far outside its cell (a clamped key): k_build, which
-            // decides such a target's candidates in FP64
-            if (fabsf(ox_t) > 4.0f * fcs || fabsf(oy_t) > 4.0f * fcs || fabsf(oz_t) > 4.0f * fcs) {
-                if (lane == 0) lcount[t] = -1;
-                continue;
-            }
-            // the target's own entry: the one hit at r^2 = 0 that is not a pair
-            const unsigned eself = (unsigned)t | (MIXED ? offset_bits(0, 0, 0) : 0u);
-            // the chunks against target t: every hit is staged (the staging area
-            // holds a whole stencil), with no exec mask change in the loop.
-            // RECORD: also note the list positions of the hits inside the band
-            // around the build radius, for the exact test below.
-            auto sweep = [&](auto record, int &m, int &nb) __attribute__((always_inline)) {
-                constexpr bool RECORD = decltype(record)::value;
-                uint64_t bandacc = 0;                     // lanes with an r^2 near the build radius
-                m = 0;
-                nb = 0;
-#pragma unroll
-                for (int j = 0; j < CH; ++j) {
-                    if (j < nch) {
-                        const float dx = ox_t - px[j], dy = oy_t - py[j], dz = oz_t - pz[j];
-                        float r2 = dx * dx + dy * dy;
-                        if constexpr (DIM == 3) r2 += dz * dz;
-                        const bool h = r2 < bhi;
-                        const uint64_t hm = __builtin_amdgcn_ballot_w64(h);
-                        int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-                        // every lane writes: a hit at its place in the list, any other
-                        // lane past the places this chunk's hits can take (later hits
-                        // overwrite it, or it lies past the list)
-                        asm volatile("" : "+v"(pos));
-                        (lst + m)[h ? pos : 64 + lane] = ent[j];
-                        if constexpr (RECORD) {
-                            const bool hb = h & !(r2 < blo);
-                            const uint64_t bm = __builtin_amdgcn_ballot_w64(hb);
-                            if (bm) {
-                                const int bp = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
-                                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bm, (uint32_t)nb));
-                                if (hb && bp < kCpBandMax) bnd[bp] = m + pos;
-                                nb += __popcll(bm);
-                            }
-                        } else {
-                            bandacc |= __builtin_amdgcn_ballot_w64(fabsf(r2 - sc.fbcut2) < bw);
-                        }
-                        m += __popcll(hm);
-                    }
-                }
-                return bandacc;
-            };
-            int m, nb;
-            if (sweep(std::false_type{}, m, nb)) {
-                // hits near the build radius: again, noting where they went (rare)
-                __builtin_amdgcn_wave_barrier();
-                sweep(std::true_type{}, m, nb);
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (nb > kCpBandMax) {
-                // rare twice over: k_build builds this target
-                if (lane == 0) lcount[t] = -1;
-                continue;
-            }
-            // the target itself is a hit (r^2 = 0): its list position
-            int sp = -1;
-            for (int b0 = 0; b0 < m && sp < 0; b0 += 64) {
-                const int i = b0 + lane;
-                const uint64_t f = __builtin_amdgcn_ballot_w64(i < m && lst[i] == eself);
-                if (f) sp = b0 + (int)__builtin_ctzll(f);
-            }
-            if (nb == 0) {
-                // the common case: the list without the target, as quads, the
-                // tail of the last quad zeroed
-                m -= sp >= 0 ? 1 : 0;
-                const int mm = min(m, cap);
-                const int q = lane, b = 4 * lane;
-                if (q < ((mm + 3) >> 2)) {
-                    const uint4 s4 = reinterpret_cast<const uint4 *>(lst)[q];
-                    const unsigned s5 = lst[b + 4];
-                    const int d = sp >= 0 ? sp - b : 4;   // entries of this quad before the target
-                    uint4 o;
-                    o.x = d > 0 ? s4.x : s4.y;
-                    o.y = d > 1 ? s4.y : s4.z;
-                    o.z = d > 2 ? s4.z : s4.w;
-                    o.w = d > 3 ? s4.w : s5;
-                    o.x = b < mm ? o.x : 0u;
-                    o.y = b + 1 < mm ? o.y : 0u;
-                    o.z = b + 2 < mm ? o.z : 0u;
-                    o.w = b + 3 < mm ? o.w : 0u;
-                    nlist[(int64_t)q * n + t] = o;
-                }
-            } else {
-                // band hits: exact tests; drop the failures and the target,
-                // keeping the order of the rest (rare)
-                if (nb > kCpBandMax) {
-                    // rare twice over: k_build builds this target
+        // the targets of the cell against the first NC chunks (NC >= nch;
+        // chunks past nch never hit): one unrolled copy per chunk count
+        auto targets = [&](auto ncc) __attribute__((always_inline)) {
+            constexpr int NC = decltype(ncc)::value;
+            for (int t = t0; t < t1; ++t) {
+                const CT ot = cpos[t];
+                const float tx = ot.x - hcs, ty = ot.y - hcs;
+                float tz = 0.0f;
+                if constexpr (DIM == 3) tz = ot.z - hcs;
+                // a target far outside its cell (a clamped key): k_build
+                if (fabsf(tx) > 4.0f * fcs || fabsf(ty) > 4.0f * fcs || fabsf(tz) > 4.0f * fcs) {
                     if (lane == 0) lcount[t] = -1;
                     continue;
                 }
-                bool fail = false;
-                int fpos = 0;
-                if (lane < nb) {
-                    fpos = bnd[lane];
-                    const unsigned e = lst[fpos];
-                    const int s = (int)(e & kSlotMask);
-                    const bool wl = (e & kWallBit) != 0u;
-                    if constexpr (MIXED) {
-                        int qi[3];
-                        V::qpos(V::loadA(rec, t), qi);
-                        double qs[3];
-                        exact_target<DIM>(qi, qs);
-                        const typename V::v4 Aj = wl ? V::wall_A(wpos[s]) : V::loadA(rec, s);
-                        fail = !(exact_r2<DIM>(qs, Aj, e) < sc.qbcut2);
-                    } else {
-                        double pi[3], pj[3], rr[3];
-                        V::pos(V::loadA(rec, t), pi);
-                        if (wl) V::wall_pos(wpos[s], pj);
-                        else V::pos(V::loadA(rec, s), pj);
-                        sub_vec<DIM>(pi, pj, rr);
-                        fail = !(norm2<DIM>(rr) < sc.bcut2);
-                    }
+                const float ct = bhi - (tx * tx + ty * ty + tz * tz);
+                // the target's own entry, the one source that is not a pair
+                const unsigned eself = (unsigned)t | (MIXED ? offset_bits(0, 0, 0) : 0u);
+                int m = 0;
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    float a = fmaf(qx[j], tx, pp[j]);
+                    a = fmaf(qy[j], ty, a);
+                    if constexpr (DIM == 3) a = fmaf(qz[j], tz, a);
+                    const bool near = a < ct, other = ent[j] != eself;
+                    const uint64_t hm = __builtin_amdgcn_ballot_w64(near) & __builtin_amdgcn_ballot_w64(other);
+                    int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+                    // every lane writes: a hit at its place in the list, any
+                    // other lane past the places this chunk's hits can take
+                    // (later hits overwrite it, or it lies past the list)
+                    asm volatile("" : "+v"(pos));
+                    (lst + m)[near && other ? pos : 64 + lane] = ent[j];
+                    m += __popcll(hm);
                 }
-                if (lane == nb) {
-                    fpos = sp;
-                    fail = sp >= 0;
-                }
-                const uint64_t dm = __builtin_amdgcn_ballot_w64(fail);
-                if (dm) {
-                    const int nd = __popcll(dm);
-                    for (int b0 = 0; b0 < m; b0 += 64) {
-                        const int i = b0 + lane;
-                        const unsigned v = i < m ? lst[i] : 0u;
-                        int before = 0;
-                        bool gone = false;
-                        for (int f = 0; f <= nb; ++f) {
-                            if (!((dm >> f) & 1ull)) continue;
-                            const int fp = __builtin_amdgcn_readlane(fpos, f);
-                            before += fp < i ? 1 : 0;
-                            gone |= fp == i;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                        if (i < m && !gone) lst[i - before] = v;
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                    m -= nd;
-                }
-                const int mm = min(m, cap);
-                const int mq = (mm + 3) & ~3;
-                if (lane < mq - mm) lst[mm + lane] = 0u;
                 __builtin_amdgcn_wave_barrier();
-                if (lane < (mq >> 2)) nlist[(int64_t)lane * n + t] = reinterpret_cast<const uint4 *>(lst)[lane];
+                // the list as quads, the tail of the last quad zeroed
+                const int mm = min(m, cap);
+                if (lane < ((mm + 3) >> 2)) {
+                    uint4 o = reinterpret_cast<const uint4 *>(lst)[lane];
+                    const int b = 4 * lane;
+                    o.y = b + 1 < mm ? o.y : 0u;
+                    o.z = b + 2 < mm ? o.z : 0u;
+                    o.w = b + 3 < mm ? o.w : 0u;
+                    nlist[(int64_t)lane * n + t] = o;
+                }
+                // LDS operations of one wave execute in order: the next
+                // target's writes come after these reads
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) {
+                    lcount[t] = m;
+                    if (m > cap) atomicOr(flags, 4u);
+                }
             }
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) {
-                lcount[t] = m;
-                if (m > cap) atomicOr(flags, 4u);
-            }
+        };
+        using std::integral_constant;
+        if constexpr (CH >= 5) {
+            if (nch <= CH - 4) targets(integral_constant<int, CH - 4>{});
+            else if (nch == CH - 3) targets(integral_constant<int, CH - 3>{});
+            else if (nch == CH - 2) targets(integral_constant<int, CH - 2>{});
+            else if (nch == CH - 1) targets(integral_constant<int, CH - 1>{});
+            else targets(integral_constant<int, CH>{});
+        } else {
+            if (nch <= 2) targets(integral_constant<int, 2>{});
+            else if (nch == 3) targets(integral_constant<int, 3>{});
+            else targets(integral_constant<int, CH>{});
         }
         t0 = t1;
     }
@@ -1319,19 +1232,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_build(
     const v4 Ai = V::loadA(rec, k);
     real pi[3];
     V::pos(Ai, pi);
-    double qs[3] = {0.0, 0.0, 0.0};
-    if constexpr (MIXED) {
-        int qi[3];
-        V::qpos(Ai, qi);
-        exact_target<DIM>(qi, qs);
-    }
     float ci[3];
     const typename Cand<DIM>::t cp = cpos[k];
     ci[0] = cp.x;
     ci[1] = cp.y;
     if constexpr (DIM == 3) ci[2] = cp.z;
     else ci[2] = 0.0f;
-    const int m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, qs, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+    const int m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
                                              nlist, cap, sc.N);
     lcount[k] = m;
     if (m > cap) atomicOr(flags, 4u);
@@ -1422,7 +1329,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     };
     if constexpr (COOP && (LIST == 3 || LIST == 5)) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED, LIST == 3, kCoopRoundsWalk>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
+        walk_coop<DIM, MIXED, NEED, density_chk<MIXED, LIST>(), kCoopRoundsWalk>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
         if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         if (!act) return;
     } else if constexpr (COOP) {
@@ -1436,14 +1343,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
                 ci[0] = cp.x; ci[1] = cp.y;
                 if constexpr (DIM == 3) ci[2] = cp.z;
                 else ci[2] = 0.0f;
-                m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, qs, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+                m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
                                                nlist, cap, n);
                 lcount[k] = m;
             } else {
                 m = lcount[k];
             }
         }
-        walk_coop<DIM, MIXED, NEED, LIST == 2, kCoopRoundsBuild>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
+        walk_coop<DIM, MIXED, NEED, density_chk<MIXED, LIST>(), kCoopRoundsBuild>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
         if (act && m > cap) {
             if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
@@ -1451,7 +1358,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         if (!act) return;
     } else if constexpr (LIST == 3 || LIST == 5) {
         const int m = lcount[k];
-        if (m <= cap) walk_list<DIM, MIXED, skin_walk_u<DIM, MIXED>(), NEED, LIST == 3>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
+        if (m <= cap) walk_list<DIM, MIXED, skin_walk_u<DIM, MIXED>(), NEED, density_chk<MIXED, LIST>()>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
         else for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
     } else if constexpr (LIST) {
         float ci[3];
@@ -1462,14 +1369,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         const bool build = LIST == 1 || *gate != 0;
         int m;
         if (build) {
-            m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, qs, ci, cstart, wstart, rec, wpos, cpos, wcpos,
+            m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
                                            nlist, cap, n);
             lcount[k] = m;
         } else {
             m = lcount[k];
         }
         if (m <= cap) {
-            walk_list<DIM, MIXED, fused_walk_u<MIXED>(), NEED, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
+            walk_list<DIM, MIXED, fused_walk_u<MIXED>(), NEED, density_chk<MIXED, LIST>()>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
         } else {
             if (build) atomicOr(flags, 4u);
             for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
@@ -1522,7 +1429,7 @@ static void build_dispatch(const SimConst &sc, const Dev &d, hipStream_t s)
                            woff < (int64_t)UINT32_MAX;
     if (cell_pair) {
         k_build_cp<DIM, MIXED, SKIN><<<d.nfchunks, d.block, 0, s>>>(
-            sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, rec, wp, cp, (uint32_t)woff, d.nlist,
+            sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, cp, (uint32_t)woff, d.nlist,
             d.lcount, d.list_cap, d.flags, d.gate);
         k_build<DIM, MIXED, SKIN, PF, true><<<d.nfchunks, d.block, 0, s>>>(
             sc, d.fmap, d.inst, d.skey, d.cell_start, d.wall_start, rec, wp, cp, wcp, d.nlist, d.lcount,
@@ -1655,14 +1562,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, MIXED, NEED_ALL, LIST == 2, coop_rounds_force<DIM, MIXED>()>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
+        walk_coop<DIM, MIXED, NEED_ALL, true, coop_rounds_force<DIM, MIXED>()>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
         if (act && m > cap)
             for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, cut2, pair);
     } else if (act) {
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
-            if (m <= cap) walk_list<DIM, MIXED, U, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
+            if (m <= cap) walk_list<DIM, MIXED, U, NEED_ALL, true>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
             else for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         } else {
             for_neighbours<DIM, MIXED, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
@@ -1910,14 +1817,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_pressure(
     if constexpr (LIST && kCoopWalk) {
         // every lane takes part in the cooperative walk
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, sc.cut2, pair);
+        walk_coop<DIM, false, NEED_ALL, true, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, sc.cut2, pair);
         if (act && m > cap)
             for_neighbours<DIM, false, NEED_ALL>(sc, I, skey[k] - I.cell_base, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
     } else if (act) {
         const int lk = skey[k] - I.cell_base;
         if constexpr (LIST) {
             const int m = lcount[k];
-            if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, sc.cut2, pair);
+            if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, true>(sc, k, m, pi, rec, wpos, nlist, n, sc.cut2, pair);
             else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
         } else {
             for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
@@ -1988,12 +1895,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_density(
     const int lk = skey[kk] - I.cell_base;
     if constexpr (LIST && kCoopWalk) {
         const int m = act ? lcount[k] : 0;
-        walk_coop<DIM, false, NEED_ALL, LIST == 2, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, sc.cut2, pair);
+        walk_coop<DIM, false, NEED_ALL, true, kCoopRoundsDual>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, sc.cut2, pair);
         if (act && m > cap) for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
         if (!act) return;
     } else if constexpr (LIST) {
         const int m = lcount[k];
-        if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, LIST == 2>(sc, k, m, pi, rec, wpos, nlist, n, sc.cut2, pair);
+        if (m <= cap) walk_list<DIM, false, kDualWalkU, NEED_ALL, true>(sc, k, m, pi, rec, wpos, nlist, n, sc.cut2, pair);
         else for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
     } else {
         for_neighbours<DIM, false, NEED_ALL>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, sc.cut2, pair);
