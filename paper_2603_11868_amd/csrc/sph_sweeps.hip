@@ -1015,7 +1015,11 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
 // not contiguous) and capacities above kCpListMax use k_build alone.
 // ---------------------------------------------------------------------------
 
-template <int DIM> constexpr int cp_chunks() { return DIM == 3 ? 10 : 4; }   // register chunks of 64 sources
+// Register chunks of 64 sources.  3D: with h = 1.3 dx a stencil of cells of
+// 2h spans 7 or 8 lattice planes per axis (at most 512 sources, walls
+// included, while the fluid stays near its rest density); cells of 2h + skin
+// reach 9 planes.
+template <int DIM, bool SKIN> constexpr int cp_chunks() { return DIM == 3 ? (SKIN ? 10 : 8) : 4; }
 constexpr int kCpListMax = 255;        // list capacity the cell-pair build supports
 
 // Value of `v` on lane `src` (lane-varying source lane).
@@ -1034,7 +1038,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     if constexpr (SKIN) {
         if (*gate == 0) return;
     }
-    constexpr int CH = cp_chunks<DIM>();
+    constexpr int CH = cp_chunks<DIM, SKIN>();
     // staging: a whole stencil of hits, and room past it for the writes of
     // the lanes without a hit
     constexpr int kCpStage = CH * 64;
@@ -1044,8 +1048,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w0 = ch.begin + wv * 64;
-    const int w1 = min(w0 + 64, ch.end);
-    if (w0 >= w1) return;                                 // the whole wave
+    const int nt = min(64, ch.end - w0);                  // targets of the wave
+    if (nt <= 0) return;                                  // the whole wave
     unsigned *lst = stage[wv];
     const InstDev &I = inst[ch.inst];
     const int ncx = I.ncell[0], ncy = I.ncell[1], ncz = I.ncell[2];
@@ -1053,43 +1057,82 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     const float bhi = sc.fbcut2 * (1.0f + 1e-4f);        // the build radius^2 with its margin
     const char *cbase = reinterpret_cast<const char *>(cpos);
     const int n = sc.N;
-    int t0 = w0;
-    while (t0 < w1) {
-        const int key = __builtin_amdgcn_readfirstlane(skey[t0]);
-        const int t1 = min(w1, __builtin_amdgcn_readfirstlane(cstart[key + 1]));
-        const int lk = key - I.cell_base;
+
+    // the wave's targets, one per lane: cell key, position relative to the
+    // centre of its cell, R^2 (1 + 1e-4) - |t|^2
+    const bool tv = lane < nt;
+    const int tl = w0 + (tv ? lane : 0);
+    const int kl = skey[tl];
+    const CT ol = cpos[tl];
+    const float txl = ol.x - hcs, tyl = ol.y - hcs;
+    float tzl = 0.0f;
+    if constexpr (DIM == 3) tzl = ol.z - hcs;
+    const float ctl = bhi - (txl * txl + tyl * tyl + tzl * tzl);
+    // targets far outside their cell (clamped keys) are left to k_build
+    const uint64_t farm = __builtin_amdgcn_ballot_w64(
+        tv && (fabsf(txl) > 4.0f * fcs || fabsf(tyl) > 4.0f * fcs || fabsf(tzl) > 4.0f * fcs));
+    // the first target of each cell: lane 0 and the lanes whose key differs
+    // from the one before
+    const int kup = lane_value(kl, lane > 0 ? lane - 1 : 0);
+    uint64_t starts = __builtin_amdgcn_ballot_w64(tv && (lane == 0 || kl != kup));
+    int lc = -1;                                          // list length of the lane's target (-1: k_build)
+    bool over = false;                                    // a list longer than cap
+
+    // the cell of the lane's target (instance-local key)
+    const int lkl = kl - I.cell_base;
+    // lane r < NR describes range r = 2 row + kind of the stencil of cell
+    // (cx, cy, cz): its first slot, length, the slots where the second and
+    // third cell of the row begin, and the row's cell offsets (x of its first
+    // cell, y, z; each plus one).  The loads are unconditional (a row outside
+    // the grid reads the instance's first row and is emptied afterwards), so
+    // that they stay in flight until the values are used.
+    const int rrow = lane >> 1, rkind = lane & 1;
+    const int rdy = (DIM == 3 ? rrow % 3 : rrow) - 1;
+    const int rdz = DIM == 3 ? rrow / 3 - 1 : 0;
+    const int *rst = rkind ? wstart : cstart;
+    struct Ranges { int start, end, b1, b2, sh; bool ok; };
+    auto ranges = [&](int lk) __attribute__((always_inline)) {
         const int cx = lk % ncx, cy = (lk / ncx) % ncy, cz = lk / (ncx * ncy);
-        // lane r < NR describes range r = 2 row + kind: its first slot, length,
-        // the slots where the second and third cell of the row begin, and the
-        // row's cell offsets (x of its first cell, y, z; each plus one)
-        int rstart = 0, rlen = 0, rb1 = 0, rb2 = 0, rsh = 0;
-        if (lane < NR) {
-            const int row = lane >> 1, kind = lane & 1;
-            const int dy = (DIM == 3 ? row % 3 : row) - 1;
-            const int dz = DIM == 3 ? row / 3 - 1 : 0;
-            const int yy = cy + dy, zz = cz + dz;
-            const int xlo = cx > 0 ? cx - 1 : cx, xhi = cx < ncx - 1 ? cx + 1 : cx;
-            if (yy >= 0 && yy < ncy && zz >= 0 && zz < ncz) {
-                const int *st = kind ? wstart : cstart;
-                const int rk = I.cell_base + (yy + ncy * zz) * ncx;
-                rstart = st[rk + xlo];
-                const int rend = st[rk + xhi + 1];
-                rlen = rend - rstart;
-                rb1 = xlo + 1 <= xhi ? st[rk + xlo + 1] : rend;
-                rb2 = xlo + 2 <= xhi ? st[rk + xlo + 2] : rend;
-            }
-            rsh = (xlo - cx + 1) | ((dy + 1) << 2) | ((dz + 1) << 4) | (kind << 6);
+        Ranges R;
+        const int yy = cy + rdy, zz = cz + rdz;
+        R.ok = lane < NR && yy >= 0 && yy < ncy && zz >= 0 && zz < ncz;
+        const int xlo = cx > 0 ? cx - 1 : cx, xhi = cx < ncx - 1 ? cx + 1 : cx;
+        const int rk = I.cell_base + (R.ok ? (yy + ncy * zz) * ncx : 0);
+        R.start = rst[rk + xlo];
+        R.end = rst[rk + xhi + 1];
+        R.b1 = rst[rk + min(xlo + 1, xhi + 1)];
+        R.b2 = rst[rk + min(xlo + 2, xhi + 1)];
+        R.sh = (xlo - cx + 1) | ((rdy + 1) << 2) | ((rdz + 1) << 4) | (rkind << 6);
+        return R;
+    };
+
+    // list output, one target behind: the quads of the last target are read
+    // from the staging before the next target's tests write it (a wave's LDS
+    // operations execute in order) and stored after them
+    int pend_t = -1, pend_mm = 0;
+    auto store_pending = [&](const uint4 &o) __attribute__((always_inline)) {
+        if (pend_t >= 0 && lane < ((pend_mm + 3) >> 2)) {
+            const int b = 4 * lane;
+            uint4 q = o;
+            q.y = b + 1 < pend_mm ? q.y : 0u;
+            q.z = b + 2 < pend_mm ? q.z : 0u;
+            q.w = b + 3 < pend_mm ? q.w : 0u;
+            nlist[(int64_t)lane * n + pend_t] = q;
         }
+    };
+
+    Ranges R = ranges(__builtin_amdgcn_readlane(lkl, 0));
+    while (true) {
+        const int a = (int)__builtin_ctzll(starts);      // the cell's first and last + 1 lanes
+        starts &= starts - 1;
+        const int b = starts ? (int)__builtin_ctzll(starts) : nt;
+        const int rstart = R.ok ? R.start : 0, rlen = R.ok ? R.end - R.start : 0;
+        const int rb1 = R.b1, rb2 = R.b2, rsh = R.sh;
         const int rend_seq = wave_inclusive_scan(rlen);  // end of range r in the sequence
         const int S = __builtin_amdgcn_readlane(rend_seq, 63);
         const int nch = (S + 63) >> 6;
-        if (nch > CH) {
-            // too many sources for the registers: k_build takes these targets
-            if (lane < t1 - t0) lcount[t0 + lane] = -1;
-            t0 = t1;
-            continue;
-        }
-        // the chunks: -2 p, |p|^2 and the entry of every source
+        // the chunks: -2 p, |p|^2 and the entry of every source (a cell with
+        // more sources than the registers hold is left to k_build)
         float qx[CH], qy[CH], qz[CH], pp[CH];
         unsigned ent[CH];
         int rc = 0;                                       // ranges ending at or before 64 j
@@ -1098,7 +1141,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
             qx[j] = qy[j] = qz[j] = 0.0f;
             pp[j] = 3.0e38f;                              // no hit
             ent[j] = 0u;
-            if (j < nch) {
+            if (j < nch && nch <= CH) {
                 const int g = 64 * j + lane;
                 while (rc < NR && __builtin_amdgcn_readlane(rend_seq, rc) <= 64 * j) ++rc;
                 // the range of g: rc plus the ranges ending inside the chunk at or before g
@@ -1131,74 +1174,72 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
                 }
             }
         }
+        // the next cell's ranges, loaded while this cell's targets are tested
+        const int nb = starts ? b : a;
+        R = ranges(__builtin_amdgcn_readlane(lkl, nb));
         // the targets of the cell against the first NC chunks (NC >= nch;
         // chunks past nch never hit): one unrolled copy per chunk count
         auto targets = [&](auto ncc) __attribute__((always_inline)) {
             constexpr int NC = decltype(ncc)::value;
-            for (int t = t0; t < t1; ++t) {
-                const CT ot = cpos[t];
-                const float tx = ot.x - hcs, ty = ot.y - hcs;
-                float tz = 0.0f;
-                if constexpr (DIM == 3) tz = ot.z - hcs;
-                // a target far outside its cell (a clamped key): k_build
-                if (fabsf(tx) > 4.0f * fcs || fabsf(ty) > 4.0f * fcs || fabsf(tz) > 4.0f * fcs) {
-                    if (lane == 0) lcount[t] = -1;
-                    continue;
-                }
-                const float ct = bhi - (tx * tx + ty * ty + tz * tz);
-                // the target's own entry, the one source that is not a pair
-                const unsigned eself = (unsigned)t | (MIXED ? offset_bits(0, 0, 0) : 0u);
+            for (int l = a; l < b; ++l) {
+                const uint4 o = reinterpret_cast<const uint4 *>(lst)[lane];   // the pending quads
+                const bool skip = (farm >> l) & 1ull;
                 int m = 0;
+                if (!skip) {
+                    const float ttx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(txl), l));
+                    const float tty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tyl), l));
+                    float ttz = 0.0f;
+                    if constexpr (DIM == 3) ttz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tzl), l));
+                    const float ct = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ctl), l));
+                    // the target's own entry, the one source that is not a pair
+                    unsigned eself = (unsigned)(w0 + l) | (MIXED ? offset_bits(0, 0, 0) : 0u);
+                    // an opaque scalar: no induction variable per chunk
+                    asm volatile("" : "+s"(eself));
 #pragma unroll
-                for (int j = 0; j < NC; ++j) {
-                    float a = fmaf(qx[j], tx, pp[j]);
-                    a = fmaf(qy[j], ty, a);
-                    if constexpr (DIM == 3) a = fmaf(qz[j], tz, a);
-                    const bool near = a < ct, other = ent[j] != eself;
-                    const uint64_t hm = __builtin_amdgcn_ballot_w64(near) & __builtin_amdgcn_ballot_w64(other);
-                    int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-                    // every lane writes: a hit at its place in the list, any
-                    // other lane past the places this chunk's hits can take
-                    // (later hits overwrite it, or it lies past the list)
-                    asm volatile("" : "+v"(pos));
-                    (lst + m)[near && other ? pos : 64 + lane] = ent[j];
-                    m += __popcll(hm);
+                    for (int j = 0; j < NC; ++j) {
+                        float d = fmaf(qx[j], ttx, pp[j]);
+                        d = fmaf(qy[j], tty, d);
+                        if constexpr (DIM == 3) d = fmaf(qz[j], ttz, d);
+                        const bool near = d < ct, other = ent[j] != eself;
+                        const uint64_t hm = __builtin_amdgcn_ballot_w64(near) & __builtin_amdgcn_ballot_w64(other);
+                        int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+                        // every lane writes: a hit at its place in the list, any
+                        // other lane past the places this chunk's hits can take
+                        // (later hits overwrite it, or it lies past the list)
+                        asm volatile("" : "+v"(pos));
+                        (lst + m)[near && other ? pos : 64 + lane] = ent[j];
+                        m += __popcll(hm);
+                    }
                 }
-                __builtin_amdgcn_wave_barrier();
-                // the list as quads, the tail of the last quad zeroed
-                const int mm = min(m, cap);
-                if (lane < ((mm + 3) >> 2)) {
-                    uint4 o = reinterpret_cast<const uint4 *>(lst)[lane];
-                    const int b = 4 * lane;
-                    o.y = b + 1 < mm ? o.y : 0u;
-                    o.z = b + 2 < mm ? o.z : 0u;
-                    o.w = b + 3 < mm ? o.w : 0u;
-                    nlist[(int64_t)lane * n + t] = o;
-                }
-                // LDS operations of one wave execute in order: the next
-                // target's writes come after these reads
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0) {
-                    lcount[t] = m;
-                    if (m > cap) atomicOr(flags, 4u);
+                store_pending(o);
+                pend_t = skip ? -1 : w0 + l;
+                pend_mm = min(m, cap);
+                if (!skip) {
+                    lc = lane == l ? m : lc;
+                    over |= m > cap;
                 }
             }
         };
         using std::integral_constant;
-        if constexpr (CH >= 5) {
-            if (nch <= CH - 4) targets(integral_constant<int, CH - 4>{});
-            else if (nch == CH - 3) targets(integral_constant<int, CH - 3>{});
-            else if (nch == CH - 2) targets(integral_constant<int, CH - 2>{});
-            else if (nch == CH - 1) targets(integral_constant<int, CH - 1>{});
-            else targets(integral_constant<int, CH>{});
-        } else {
-            if (nch <= 2) targets(integral_constant<int, 2>{});
-            else if (nch == 3) targets(integral_constant<int, 3>{});
-            else targets(integral_constant<int, CH>{});
+        if (nch <= CH) {
+            if constexpr (CH >= 5) {
+                if (nch <= CH - 4) targets(integral_constant<int, CH - 4>{});
+                else if (nch == CH - 3) targets(integral_constant<int, CH - 3>{});
+                else if (nch == CH - 2) targets(integral_constant<int, CH - 2>{});
+                else if (nch == CH - 1) targets(integral_constant<int, CH - 1>{});
+                else targets(integral_constant<int, CH>{});
+            } else {
+                if (nch <= 2) targets(integral_constant<int, 2>{});
+                else if (nch == 3) targets(integral_constant<int, 3>{});
+                else targets(integral_constant<int, CH>{});
+            }
         }
-        t0 = t1;
+        if (!starts) break;
     }
+    store_pending(reinterpret_cast<const uint4 *>(lst)[lane]);
+    if (tv) lcount[w0 + lane] = lc;
+    if (over && lane == 0) atomicOr(flags, 4u);
 }
 
 // Candidate tests and list build alone (kSplitBuild): lists of every target
