@@ -101,6 +101,20 @@ typedef enum {
 #define SPH_FLAG_NONFINITE 2u   /* a reduction saw a non-finite max|v| or max|a| */
 #define SPH_FLAG_CAPACITY  4u   /* a neighbour list overflowed (handled, slower) */
 
+/* Where the step runs.  SPH_POLICY_DEVICE: the HIP kernels on the current
+ * GPU (buffers are device memory).  SPH_POLICY_HOST: the same per-particle and
+ * per-pair bodies on the host's threads over host memory, the host execution
+ * policy of the paper's single-source kernels (Sec. 4); FP64, the WCSPH
+ * scheme without a skin, row-major keys; sph_prime and sph_step_batched only
+ * (the stage calls, timing and sph_bind_static return SPH_E_UNSUPPORTED); no
+ * workspace (sph_workspace_size gives 0); threads: the environment variable
+ * SPH_HOST_THREADS, else the hardware concurrency.  Never chosen by the
+ * library on its own: a device context never falls back to the host. */
+typedef enum {
+    SPH_POLICY_DEVICE = 0,
+    SPH_POLICY_HOST = 1
+} sph_policy;
+
 typedef struct {
     int32_t n_fluid;         /* fluid particles of this instance (>= 0) */
     int32_t n_wall;          /* fixed wall particles of this instance (>= 0) */
@@ -161,8 +175,8 @@ typedef struct {
                                 a cell's stencil held by the lanes of a wave,
                                 the cell's targets taken one at a time;
                                 row-major keys and list_cap <= 255, else one
-                                lane per target).  All give the same lists */
-    int32_t reserved;
+                                lane per target).  All give the same results */
+    int32_t policy;          /* sph_policy: where the step runs (below) */
 } sph_params;
 
 typedef struct {

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsph.so")
-SOURCES = ("sph_abi.hip", "sph_sort.hip", "sph_kernels.hip", "sph_sweeps.hip")
+SOURCES = ("sph_abi.hip", "sph_sort.hip", "sph_kernels.hip", "sph_sweeps.hip", "sph_host.hip")
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
 
 

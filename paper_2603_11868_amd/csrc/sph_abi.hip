@@ -1,14 +1,18 @@
 // C ABI of libsph (declared in include/sph.h): argument checking, derived
 // constants, the workspace layout, the chunk maps and the stage sequences.
 #include "sph.h"
+#include "sph_host.h"
 #include "sph_launch.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace sphx;
@@ -100,6 +104,8 @@ struct sph_ctx {
     bool mixed = false;
     bool dual = false;        // dual-criteria Riemann scheme
     bool skin = false;        // Verlet skin: the device decides when to rebuild
+    bool host = false;        // SPH_POLICY_HOST: the step runs on the host
+    std::unique_ptr<HostExec> hexec;
     // workspace layout (byte offsets)
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
@@ -526,6 +532,14 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     if (p->scheme != SPH_SCHEME_WCSPH && p->scheme != SPH_SCHEME_DUAL) return fail(SPH_E_ARG, "unknown scheme");
     if (p->key_order != SPH_KEYS_ROW_MAJOR && p->key_order != SPH_KEYS_MORTON_TILES)
         return fail(SPH_E_ARG, "unknown key order");
+    if (p->policy != SPH_POLICY_DEVICE && p->policy != SPH_POLICY_HOST) return fail(SPH_E_ARG, "unknown policy");
+    if (p->policy == SPH_POLICY_HOST) {
+        if (p->precision != SPH_FP64) return fail(SPH_E_UNSUPPORTED, "the host policy runs in FP64 only");
+        if (p->scheme != SPH_SCHEME_WCSPH) return fail(SPH_E_UNSUPPORTED, "the host policy runs the WCSPH scheme");
+        if (p->skin != 0.0) return fail(SPH_E_UNSUPPORTED, "the host policy rebuilds the cells every step (skin = 0)");
+        if (p->key_order != SPH_KEYS_ROW_MAJOR) return fail(SPH_E_UNSUPPORTED, "the host policy uses row-major keys");
+        if (p->use_graph) return fail(SPH_E_UNSUPPORTED, "the host policy replays no graphs");
+    }
     if (p->scheme == SPH_SCHEME_DUAL) {
         if (p->precision != SPH_FP64) return fail(SPH_E_UNSUPPORTED, "the dual scheme runs in FP64 only");
         if (p->use_graph) return fail(SPH_E_UNSUPPORTED, "the dual scheme does not replay graphs");
@@ -541,6 +555,7 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     c->mixed = p->precision == SPH_MIXED;
     c->dual = p->scheme == SPH_SCHEME_DUAL;
     c->skin = p->skin > 0.0;
+    c->host = p->policy == SPH_POLICY_HOST;
     c->inst.assign(p->inst, p->inst + p->n_instances);
     const double cs = 2.0 * p->h + p->skin;
     int64_t N = 0, Nw = 0, C = 0;
@@ -628,7 +643,8 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     build_layout(c);
     // the list walks address fluid and padded wall records with 32-bit byte
     // offsets from one base
-    if (lcap > 0 && (uint64_t)c->sc.wrec_off + (uint64_t)std::max<int64_t>(Nw, 1) * wall_rec_bytes(p->dim, c->mixed) + 64 >= (1ull << 32)) {
+    if (c->host) c->ws_bytes = 0;   // the host executor keeps its scratch itself
+    if (!c->host && lcap > 0 && (uint64_t)c->sc.wrec_off + (uint64_t)std::max<int64_t>(Nw, 1) * wall_rec_bytes(p->dim, c->mixed) + 64 >= (1ull << 32)) {
         delete c;
         return fail(SPH_E_CAPACITY, "the neighbour-list walks address at most 4 GiB of sweep records; use list_cap = -1");
     }
@@ -692,6 +708,21 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     if (c->N > 0 && (!b->x || !b->v || !b->a || !b->rho || !b->id || !b->key || !b->perm || !b->count))
         return fail(SPH_E_ARG, "missing fluid buffer");
     if (c->Nw > 0 && (!b->xw || !b->wall_perm)) return fail(SPH_E_ARG, "missing wall buffer");
+    if (c->host) {
+        if (!b->cell_start || !b->wall_start || !b->dt || !b->diag)
+            return fail(SPH_E_ARG, "missing table or per-instance buffer");
+        int nt = (int)std::thread::hardware_concurrency();
+        if (const char *e = std::getenv("SPH_HOST_THREADS")) nt = std::atoi(e);
+        c->hexec.reset(new HostExec(c->sc, c->idev, c->p.reorder_every, nt > 0 ? nt : 1));
+        c->buf = *b;
+        c->hexec->bind(*b);
+        c->bound = true;
+        c->primed = false;
+        c->cells_built = false;
+        c->steps_done = 0;
+        c->substeps_done = 0;
+        return SPH_OK;
+    }
     if (!b->cell_start || !b->wall_start || !b->dt || !b->diag || !b->workspace)
         return fail(SPH_E_ARG, "missing table, per-instance or workspace buffer");
     if (reinterpret_cast<uintptr_t>(b->workspace) % 256 != 0) return fail(SPH_E_ARG, "workspace must be 256-byte aligned");
@@ -806,6 +837,7 @@ sph_status static_scratch_address(void **out)
 
 sph_status sph_bind_static(sph_ctx *c, const sph_buffers *b, void *stream)
 {
+    if (c && c->host) return fail(SPH_E_UNSUPPORTED, "the host policy takes no device scratch");
     if (!c || !b) return fail(SPH_E_ARG, "null argument");
     if (c->ws_bytes > (size_t)SPH_STATIC_SCRATCH_BYTES)
         return fail(SPH_E_CAPACITY, "workspace of " + std::to_string(c->ws_bytes) +
@@ -824,6 +856,12 @@ sph_status sph_prime(sph_ctx *c, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->host) {
+        c->hexec->prime();
+        c->primed = true;
+        c->steps_done = 0;
+        return SPH_OK;
+    }
     hipStream_t s = as_stream(stream);
     const Dev &d = c->dev;
     HIP_TRY(launch_fill_f64(d.diag, (int64_t)c->idev.size() * SPH_NDIAG, 0.0, s));
@@ -850,6 +888,7 @@ sph_status sph_build_cells(sph_ctx *c, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->host) return fail(SPH_E_UNSUPPORTED, "the host policy runs whole steps (sph_step_batched)");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     if (c->cells_built) return fail(SPH_E_STATE, "cells already built: call sph_sort first");
@@ -862,6 +901,7 @@ sph_status sph_sort(sph_ctx *c, int32_t reorder, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->host) return fail(SPH_E_UNSUPPORTED, "the host policy runs whole steps (sph_step_batched)");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     if (!c->cells_built) return fail(SPH_E_STATE, "sph_build_cells (or sph_integrate half 1) first");
@@ -874,6 +914,7 @@ sph_status sph_density(sph_ctx *c, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->host) return fail(SPH_E_UNSUPPORTED, "the host policy runs whole steps (sph_step_batched)");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     return do_density(c, 1, as_stream(stream), c->timing);
@@ -883,6 +924,7 @@ sph_status sph_forces(sph_ctx *c, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->host) return fail(SPH_E_UNSUPPORTED, "the host policy runs whole steps (sph_step_batched)");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     return do_force(c, 0, as_stream(stream), c->timing);
@@ -892,6 +934,7 @@ sph_status sph_integrate(sph_ctx *c, int32_t half, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->host) return fail(SPH_E_UNSUPPORTED, "the host policy runs whole steps (sph_step_batched)");
     if (c->dual) return fail(SPH_E_UNSUPPORTED, "stage calls are for the WCSPH scheme");
     if (c->skin) return fail(SPH_E_UNSUPPORTED, "stage calls rebuild every step: use skin = 0");
     if (half != 1 && half != 2) return fail(SPH_E_ARG, "half must be 1 or 2");
@@ -914,6 +957,13 @@ sph_status sph_step_batched(sph_ctx *c, int32_t n_steps, void *stream)
     if (n_steps < 0) return fail(SPH_E_ARG, "n_steps must be >= 0");
     if (!c->bound || !c->primed) return fail(SPH_E_STATE, "sph_bind and sph_prime first");
     if (c->cells_built) return fail(SPH_E_STATE, "a staged step is half done");
+    if (c->host) {
+        for (int32_t it = 0; it < n_steps; ++it) {
+            c->hexec->step();
+            c->steps_done += 1;
+        }
+        return SPH_OK;
+    }
     hipStream_t s = as_stream(stream);
     if (c->dual) {
         for (int32_t it = 0; it < n_steps; ++it) {
@@ -967,6 +1017,11 @@ sph_status sph_poll_errors(sph_ctx *c, uint32_t *flags, void *stream)
 {
     if (!c || !flags) return fail(SPH_E_ARG, "null argument");
     if (!c->bound) return fail(SPH_E_STATE, "sph_bind first");
+    if (c->host) {
+        *flags = c->hexec->flags();
+        c->hexec->clear_flags();
+        return SPH_OK;
+    }
     hipStream_t s = as_stream(stream);
     unsigned host = 0;
     HIP_TRY(hipMemcpyAsync(&host, c->dev.flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
@@ -980,6 +1035,7 @@ sph_status sph_poll_errors(sph_ctx *c, uint32_t *flags, void *stream)
 sph_status sph_set_timing_mask(sph_ctx *c, uint32_t mask)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
+    if (c->host && mask) return fail(SPH_E_UNSUPPORTED, "HIP events time the device policy only");
     c->timing_mask = mask & ((1u << ST_COUNT) - 1u);
     c->timing = c->timing_mask != 0;
     return SPH_OK;
@@ -988,6 +1044,7 @@ sph_status sph_set_timing_mask(sph_ctx *c, uint32_t mask)
 sph_status sph_set_timing(sph_ctx *c, int32_t enable)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
+    if (c->host && enable) return fail(SPH_E_UNSUPPORTED, "HIP events time the device policy only");
     c->timing = enable != 0;
     c->timing_mask = enable != 0 ? (1u << ST_COUNT) - 1u : 0u;
     return SPH_OK;
@@ -996,6 +1053,7 @@ sph_status sph_set_timing(sph_ctx *c, int32_t enable)
 sph_status sph_stage_times(sph_ctx *c, double *ms, int64_t *launches, int32_t n, int32_t reset, void *stream)
 {
     if (!c) return fail(SPH_E_ARG, "null context");
+    if (c->host) return fail(SPH_E_UNSUPPORTED, "HIP events time the device policy only");
     HIP_TRY(hipStreamSynchronize(as_stream(stream)));
     collect_times(c);
     for (int32_t i = 0; i < n && i < ST_COUNT; ++i) {

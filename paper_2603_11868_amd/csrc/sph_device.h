@@ -99,19 +99,19 @@ template <> struct Rec<3, true>  { using v4 = fvec4; using v2 = fvec2; using wpo
 // sorted order in every direction.  Tiles past the grid's edge are padded:
 // their cells stay empty.
 
-__device__ __forceinline__ int spread_bits(int v, int dim)      // 3 bits -> every dim-th bit
+__host__ __device__ __forceinline__ int spread_bits(int v, int dim)      // 3 bits -> every dim-th bit
 {
     return dim == 3 ? ((v & 1) | ((v & 2) << 2) | ((v & 4) << 4))
                     : ((v & 1) | ((v & 2) << 1) | ((v & 4) << 2));
 }
 
-__device__ __forceinline__ int gather_bits(int m, int dim)      // inverse of spread_bits
+__host__ __device__ __forceinline__ int gather_bits(int m, int dim)      // inverse of spread_bits
 {
     return dim == 3 ? ((m & 1) | ((m >> 2) & 2) | ((m >> 4) & 4))
                     : ((m & 1) | ((m >> 1) & 2) | ((m >> 2) & 4));
 }
 
-__device__ __forceinline__ int cell_key(const SimConst &sc, const InstDev &I, int cx, int cy, int cz)
+__host__ __device__ __forceinline__ int cell_key(const SimConst &sc, const InstDev &I, int cx, int cy, int cz)
 {
     if (sc.key_order == 0) return cx + I.ncell[0] * (cy + I.ncell[1] * cz);
     const int ntx = (I.ncell[0] + 7) >> 3, nty = (I.ncell[1] + 7) >> 3;
@@ -121,7 +121,7 @@ __device__ __forceinline__ int cell_key(const SimConst &sc, const InstDev &I, in
     return (tile << (3 * sc.dim)) | m;
 }
 
-__device__ __forceinline__ void cell_coords(const SimConst &sc, const InstDev &I, int lk, int &cx, int &cy,
+__host__ __device__ __forceinline__ void cell_coords(const SimConst &sc, const InstDev &I, int lk, int &cx, int &cy,
                                             int &cz)
 {
     if (sc.key_order == 0) {

@@ -55,16 +55,6 @@ hipError_t launch_fill_f64(double *p, int64_t n, double val, hipStream_t s)
 // keys
 // ---------------------------------------------------------------------------
 
-// floor((x - lo) * inv_cs) clamped to [0, n); subtract then multiply, no FMA.
-__device__ __forceinline__ int cell_1d(double x, double lo, double inv_cs, int n, int &clamped)
-{
-#pragma clang fp contract(off)
-    const double t = floor((x - lo) * inv_cs);
-    if (!(t >= 0.0)) { clamped = 1; return 0; }
-    if (t >= (double)n) { clamped = 1; return n - 1; }
-    return (int)t;
-}
-
 // cnt[key] += 1 for every valid lane, one atomic per distinct key of the wave.
 __device__ __forceinline__ void aggregated_count(int *cnt, int key, bool valid)
 {
@@ -422,23 +412,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
         double *d = diag + (int64_t)b * 16;
         const double dt_used = prime ? 0.0 : dt[b];
         const double vmax = tot[P_VMAX], amax = tot[P_AMAX];
-        d[0] = vmax;
-        d[1] = amax;
-        d[2] = sc.mass * (double)I.n_fluid;
-        for (int c = 0; c < 3; ++c) d[3 + c] = tot[P_MOM + c];
-        d[6] = tot[P_KE];
-        d[7] = tot[P_PE];
-        d[8] = tot[P_IE];
-        const double ff = sqrt(tot[P_FF] * tot[P_FF] + tot[P_FF + 1] * tot[P_FF + 1] +
-                               tot[P_FF + 2] * tot[P_FF + 2]);
-        d[9] = ff;
-        d[10] = I.n_fluid > 0 ? tot[P_RHO] / ((double)I.n_fluid * sc.rho0) - 1.0 : 0.0;
-        d[11] += (double)clampc[b];
+        fill_diag(sc, I, tot, dt_used, clampc[b], prime, d);
         clampc[b] = 0;
-        d[12] = tot[P_PAIRS];
-        d[13] += dt_used * ff;
-        d[14] += dt_used;
-        d[15] = prime ? 0.0 : d[15] + 1.0;
         if (sc.scheme == 1) {
             // dual-criteria plan of the next advection step: Dt from the
             // flow speed (floored at c0 / 10), equal acoustic sub-steps
@@ -452,9 +427,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
             dtsub[b] = Dt / (double)ns;
             atomicMax(nsub_max, ns);
         } else {
-            const double dt_ac = sc.cfl_ac * sc.h / (I.c0 + vmax);
-            const double dt_f = sc.cfl_f * sqrt(sc.h / amax);
-            dt[b] = dt_ac < dt_f ? dt_ac : dt_f;
+            dt[b] = cfl_dt(sc, I.c0, vmax, amax);
             if (gate) skin_plan(sc, gate, disp, dt[b], vmax, amax);
         }
         if (tot[P_BAD] > 0.0) atomicOr(flags, 2u);

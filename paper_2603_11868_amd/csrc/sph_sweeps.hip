@@ -1184,7 +1184,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
             for (int l = a; l < b; ++l) {
                 const uint4 o = reinterpret_cast<const uint4 *>(lst)[lane];   // the pending quads
                 const bool skip = (farm >> l) & 1ull;
-                int m = 0;
+                unsigned *lp = lst;                       // the target's next list place
                 if (!skip) {
                     const float ttx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(txl), l));
                     const float tty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tyl), l));
@@ -1208,10 +1208,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
                         // other lane past the places this chunk's hits can take
                         // (later hits overwrite it, or it lies past the list)
                         asm volatile("" : "+v"(pos));
-                        (lst + m)[near && other ? pos : 64 + lane] = ent[j];
-                        m += __popcll(hm);
+                        lp[near && other ? pos : 64 + lane] = ent[j];
+                        lp += __popcll(hm);
                     }
                 }
+                const int m = (int)(lp - lst);
                 store_pending(o);
                 pend_t = skip ? -1 : w0 + l;
                 pend_mm = min(m, cap);
@@ -1361,11 +1362,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
             }
         } else {
             (void)e;
-            real W, F;
-            kernel_WF(r2, (real)sc.inv_h, (real)sc.kW, (real)sc.kF, W, F);
-            sigma += W;
-            drho += vr * F;
-            ++cnt;
+            (void)vr;
+            density_pair<DIM, real>(r, r2, vi, vj, (real)sc.inv_h, (real)sc.kW, (real)sc.kF, sigma, drho, cnt);
         }
     };
     if constexpr (COOP && (LIST == 3 || LIST == 5)) {
@@ -1427,16 +1425,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     }
     const int i = perm[k];
     const double sig = MIXED ? sc.W0 + sigma : sigma;
-    const double rho_sum = sc.mass * sig;
     const double dtb = use_dt ? dt[ch.inst] : 0.0;
     // mixed path: the continuity sum is in units of cs
     const double mscale = MIXED ? sc.mass * sc.cs : sc.mass;
-    const double rho_star = rho[i] + dtb * (mscale * (double)drho);
-    const double excess = rho_star - rho_sum;
-    const double rn = excess > 0.0 ? rho_sum + excess * sc.rho0 / rho_star : rho_sum;
-    double p = I.c0 * I.c0 * (rn - sc.rho0);
-    if (p < 0.0) p = 0.0;
-    const double P = p / (rn * rn);
+    double rn, P;
+    density_update(rho[i], sig, mscale * (double)drho, dtb, sc.mass, sc.rho0, I.c0, rn, P);
     rho[i] = rn;
     count[i] = cnt;
     typename V::v2 out;
@@ -1569,36 +1562,28 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     const real gy = MIXED ? (real)sc.ug[1] : (real)sc.g[1];
     const real gz = MIXED ? (real)sc.ug[2] : (real)sc.g[2];
     const real cut2 = walk_cut2<MIXED>(sc);
+    ForceTarget<real> T;
+    T.vi[0] = vi[0];
+    T.vi[1] = vi[1];
+    T.vi[2] = vi[2];
+    T.rho_i = rho_i;
+    T.P_i = P_i;
+    T.p_i = p_i;
+    T.inv_rho_i2 = inv_rho_i2;
+    T.inv_h = inv_h;
+    T.kF = kF;
+    T.visc_a = visc_a;
+    T.eps_h2 = eps_h2;
+    T.g[0] = gx;
+    T.g[1] = gy;
+    T.g[2] = gz;
     real acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
     int cnt = 0;
     auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj, unsigned)
         __attribute__((always_inline)) {
-        // branch-free: lanes of a wave mix fluid and wall sources
-        real F;
-        kernel_F(r2, inv_h, kF, F);
         real vj[3];
         V::vel(Aj, Bj, vj);                // zero for walls
-        real vr = (vi[0] - vj[0]) * r[0] + (vi[1] - vj[1]) * r[1];
-        if constexpr (DIM == 3) vr += (vi[2] - vj[2]) * r[2];
-        real gr = gx * r[0] + gy * r[1];
-        if constexpr (DIM == 3) gr += gz * r[2];
-        real p_m = p_i - rho_i * gr;       // wall mirror: p_i + rho_i g.(x_j - x_i)
-        p_m = p_m < (real)0 ? (real)0 : p_m;
-        const real rho_j = wall ? rho_i : V::rho(Bj);
-        const real P_j = wall ? p_m * inv_rho_i2 : V::P(Bj);
-        real visc = 0;
-        if (vr < (real)0) {
-            const real den = (real)0.5 * (rho_i + rho_j) * (r2 + eps_h2);
-            visc = -visc_a * vr * recip(den);
-        }
-        const real coef = (P_i + P_j + visc) * F;
-        const real coef_ff = wall ? (real)0 : coef;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            acc[c] -= coef * r[c];
-            aff[c] -= coef_ff * r[c];
-        }
-        ++cnt;
+        force_pair<DIM, real>(T, wall, r, r2, vj, V::rho(Bj), V::P(Bj), acc, aff, cnt);
     };
     if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk

@@ -42,6 +42,7 @@ SPH_STATIC_SCRATCH_BYTES = 32 << 20
 
 SPH_SCHEME_WCSPH, SPH_SCHEME_DUAL = 0, 1
 SPH_KEYS_ROW_MAJOR, SPH_KEYS_MORTON_TILES = 0, 1
+SPH_POLICY_DEVICE, SPH_POLICY_HOST = 0, 1
 # parameters of the dual-criteria scheme as published (advection and acoustic
 # Courant numbers, dissipation limiter slope)
 DUAL_CFL_ADV, DUAL_CFL_AC, DUAL_ETA = 0.25, 0.6, 3.0
@@ -67,7 +68,7 @@ class sph_params(C.Structure):
                 ("use_graph", C.c_int32), ("list_cap", C.c_int32),
                 ("prefetch", C.c_int32), ("scheme", C.c_int32), ("key_order", C.c_int32),
                 ("cfl_adv", C.c_double), ("eta", C.c_double), ("skin", C.c_double),
-                ("build", C.c_int32), ("reserved", C.c_int32)]
+                ("build", C.c_int32), ("policy", C.c_int32)]
 
 
 class sph_buffers(C.Structure):
@@ -270,7 +271,10 @@ class Simulation:
                  use_graph=False, device="cuda", alpha=None, g=None,
                  cfl=None, velocities=None, densities=None, list_cap=0, prefetch=0,
                  scheme="wcsph", skin=0.0, key_order="row", static_scratch=False, build=None,
-                 tuned=False):
+                 tuned=False, policy="device"):
+        """policy: "device" (the HIP kernels; buffers in GPU memory) or "host"
+        (the same step bodies on the host's threads; buffers in host memory,
+        FP64 only).  The host policy is used only when asked for."""
         import torch
         self.torch = torch
         self.case = case
@@ -291,6 +295,14 @@ class Simulation:
                     prefetch = self.tuned.get("prefetch", 0)
         if build is None:
             build = 0
+        if policy not in ("device", "host"):
+            raise ValueError(f"unknown policy {policy!r}")
+        self.policy = policy
+        # host contexts take no stream (calls with None would ask torch for
+        # the current GPU stream)
+        self._s = 0 if policy == "host" else None
+        if policy == "host":
+            device = "cpu"
         self.dim = dim = case.dim
         self.device = torch.device(device)
         B = len(case.instances)
@@ -324,6 +336,7 @@ class Simulation:
         p.build = int(build)
         p.skin = float(skin)               # Verlet skin, a length (0: none)
         p.key_order = {"row": SPH_KEYS_ROW_MAJOR, "morton": SPH_KEYS_MORTON_TILES}[key_order]
+        p.policy = SPH_POLICY_HOST if policy == "host" else SPH_POLICY_DEVICE
         if scheme == "dual":
             p.scheme = SPH_SCHEME_DUAL
             p.cfl_ac = DUAL_CFL_AC if cfl is None else float(cfl)
@@ -365,8 +378,9 @@ class Simulation:
         self.wall_start = torch.zeros(Cn + 1, dtype=i32, device=dev)
         self.dt = torch.zeros(B, dtype=f64, device=dev)
         self.diag = torch.zeros((B, SPH_NDIAG), dtype=f64, device=dev)
-        if static_scratch:
-            # the library's own workspace (sph_bind_static): nothing allocated here
+        if static_scratch or policy == "host":
+            # the library's own workspace (sph_bind_static), or none (the host
+            # policy keeps its scratch itself): nothing allocated here
             self.workspace = None
             wptr = 0
         else:
@@ -385,7 +399,7 @@ class Simulation:
         if static_scratch:
             sph_bind_static(self.ctx, bufs)
         else:
-            sph_bind(self.ctx, bufs)
+            sph_bind(self.ctx, bufs, stream=self._s)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
@@ -400,28 +414,28 @@ class Simulation:
 
     # -- stages --------------------------------------------------------------
     def prime(self):
-        sph_prime(self.ctx)
+        sph_prime(self.ctx, stream=self._s)
 
     def step(self, n=1):
-        sph_step_batched(self.ctx, n)
+        sph_step_batched(self.ctx, n, stream=self._s)
 
     def build_cells(self):
-        sph_build_cells(self.ctx)
+        sph_build_cells(self.ctx, stream=self._s)
 
     def sort(self, reorder=False):
-        sph_sort(self.ctx, int(reorder))
+        sph_sort(self.ctx, int(reorder), stream=self._s)
 
     def density(self):
-        sph_density(self.ctx)
+        sph_density(self.ctx, stream=self._s)
 
     def forces(self):
-        sph_forces(self.ctx)
+        sph_forces(self.ctx, stream=self._s)
 
     def integrate(self, half):
-        sph_integrate(self.ctx, half)
+        sph_integrate(self.ctx, half, stream=self._s)
 
     def poll_errors(self):
-        return sph_poll_errors(self.ctx)
+        return sph_poll_errors(self.ctx, stream=self._s)
 
     def grid(self, b=0):
         return sph_get_grid(self.ctx, b)
@@ -431,10 +445,11 @@ class Simulation:
         return int(sph_get_info(self.ctx).steps_done)
 
     def cell_builds(self):
-        return sph_cell_builds(self.ctx)
+        return sph_cell_builds(self.ctx, stream=self._s)
 
     def synchronize(self):
-        self.torch.cuda.synchronize(self.device)
+        if self.policy == "device":
+            self.torch.cuda.synchronize(self.device)
 
     # -- host copies ---------------------------------------------------------
     def host(self):
