@@ -134,7 +134,7 @@ def morton_key(cx, cy, cz, nc, dim):
 
 def kernel_source_hash():
     hsh = hashlib.sha256()
-    for name in ("sph_sweeps.hip", "sph_step_common.h", "sph_device.h"):
+    for name in ("sph_sweeps.hip", "sph_step_common.h", "sph_device.h", "sph_bodies.h"):
         with open(os.path.join(ROOT, "paper_2603_11868_amd", "csrc", name), "rb") as f:
             hsh.update(f.read())
     return hsh.hexdigest()[:16]

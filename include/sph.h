@@ -155,9 +155,9 @@ typedef struct {
                                 from sph_create). */
     int32_t prefetch;        /* candidate records in flight per thread in the
                                 density sweep: 0 = default (8), 4 or 8 */
-    int32_t scheme;          /* sph_scheme.  SPH_SCHEME_DUAL needs SPH_FP64 and
-                                use_graph = 0; cfl_ac is then the Courant number
-                                of the acoustic sub-steps (0.6 in the published
+    int32_t scheme;          /* sph_scheme.  SPH_SCHEME_DUAL needs SPH_FP64;
+                                cfl_ac is then the Courant number of the
+                                acoustic sub-steps (0.6 in the published
                                 scheme), alpha, eps and cfl_f are unused */
     int32_t key_order;       /* sph_key_order of the cell keys (the order of
                                 the particle sort and of cell_start) */
@@ -214,7 +214,8 @@ typedef struct {
     int64_t steps_done;      /* steps since sph_prime */
     int64_t substeps_done;   /* SPH_SCHEME_DUAL: acoustic sub-steps since
                                 sph_prime (per step, the largest count over
-                                the instances) */
+                                the instances); counted on the device, so
+                                sph_get_info then waits for the device */
 } sph_info;
 
 typedef struct sph_ctx sph_ctx;
@@ -314,9 +315,12 @@ sph_status sph_integrate(sph_ctx *ctx, int32_t half, void *stream);
  * reductions.  dt stays on the device; asynchronous.  (Sec. 4 and 5 for the
  * stages; the instances batched into the same launches are this library's.)
  *
- * With SPH_SCHEME_DUAL a step is one advection step of every instance, and
- * each advection step reads the largest planned sub-step count back to the
- * host (one synchronisation of `stream` per step).  The scheme (the library
+ * With SPH_SCHEME_DUAL a step is one advection step of every instance.  The
+ * plan stays on the device: an advection step enqueues
+ * ceil(11 cfl_adv / cfl_ac) sub-step slots (the most sub-steps the plan below
+ * can ask for: n peaks at max|v| = c0 / 10), and each instance runs the first
+ * n of them; no host synchronisation, so use_graph replays whole advection
+ * steps too.  The scheme (the library
  * behind the paper, SPHinXsys; Zhang, Hu & Adams 2017 and Zhang, Rezavand &
  * Hu 2021 for the published method):
  *   advection  keys, sort, ranges (reorder every K advection steps) and the

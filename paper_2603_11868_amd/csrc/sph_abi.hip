@@ -110,7 +110,7 @@ struct sph_ctx {
     size_t ws_bytes = 0;
     size_t o_skey, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_part, o_cnt, o_rec,
         o_wkey, o_wskey, o_partials, o_rmap, o_subpart, o_fmap, o_wmap, o_inst, o_flags, o_clampc, o_nlist,
-        o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax, o_gate, o_disp, o_xb;
+        o_lcount, o_cpos, o_wcpos, o_drho, o_nsub, o_dtsub, o_nsubmax, o_subtot, o_gate, o_disp, o_xb;
     // state
     bool bound = false, primed = false, cells_built = false;
     sph_buffers buf{};
@@ -237,6 +237,7 @@ void build_layout(sph_ctx *c)
     c->o_nsub = take(sizeof(int) * c->idev.size());
     c->o_dtsub = take(sizeof(double) * c->idev.size());
     c->o_nsubmax = take(sizeof(int));
+    c->o_subtot = take(sizeof(unsigned long long));
     // Verlet skin: rebuild / reorder gates, counters and displacement bounds
     c->o_gate = take(sizeof(int) * 8);
     c->o_disp = take(sizeof(double) * 2);
@@ -422,29 +423,27 @@ sph_status dual_prime(sph_ctx *c, hipStream_t s)
     TRY(check_launch(launch_fill_f64(d.drho, c->N, 0.0, s), "fill"));
     TRY(check_launch(launch_fill_i32(d.nsub, B, 1, s), "fill"));
     TRY(check_launch(launch_fill_f64(d.dtsub, B, 0.0, s), "fill"));
+    TRY(check_launch(launch_fill_i32(reinterpret_cast<int *>(d.subs_total), 2, 0, s), "fill"));
     TRY(do_dual_part(c, 0, 0, s, false));
     TRY(do_dual_part(c, 0, 1, s, false));
     return dual_reduce(c, 1, s, false);
 }
 
 // One advection step: cell table, records and summation (with the list) at
-// the current positions, then the planned acoustic sub-steps.  Reads the
-// largest sub-step count back to the host first (one synchronisation).
-sph_status dual_advection_step(sph_ctx *c, hipStream_t s, bool timed)
+// the current positions, then nsub_bound acoustic sub-step slots, of which
+// each instance runs the ones its plan asks for (the kernels of a later slot
+// return at once).  No host synchronisation: the step can be captured.
+sph_status dual_advection_step(sph_ctx *c, bool reorder, hipStream_t s, bool timed)
 {
     const Dev &d = c->dev;
-    int nmax = 0;
-    HIP_TRY(hipMemcpyAsync(&nmax, d.nsub_max, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (nmax < 1 || nmax > (1 << 20)) return fail(SPH_E_STATE, "invalid sub-step plan (non-finite velocities?)");
+    TRY(check_launch(launch_count_substeps(d, s), "sub-step count"));
     TRY(do_keys(c, 0, s, timed));
-    TRY(do_sort(c, reorder_due(c), s, timed));
+    TRY(do_sort(c, reorder, s, timed));
     if (d.gate) TRY(check_launch(launch_save_build_positions(c->sc, d, s), "build positions"));
     TRY(do_density(c, 0, s, timed));
     TRY(check_launch(launch_fill_f64(d.drho, c->N, 0.0, s), "fill"));
-    for (int sub = 0; sub < nmax; ++sub)
+    for (int sub = 0; sub < c->sc.nsub_bound; ++sub)
         for (int part = 0; part < 4; ++part) TRY(do_dual_part(c, sub, part, s, timed));
-    c->substeps_done += nmax;
     return dual_reduce(c, 0, s, timed);
 }
 
@@ -463,7 +462,8 @@ sph_status ensure_graph(sph_ctx *c, int variant)
     if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    sph_status st = enqueue_step(c, variant == 1, c->cap_stream, false);
+    sph_status st = c->dual ? dual_advection_step(c, variant == 1, c->cap_stream, false)
+                            : enqueue_step(c, variant == 1, c->cap_stream, false);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != SPH_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -542,7 +542,6 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     }
     if (p->scheme == SPH_SCHEME_DUAL) {
         if (p->precision != SPH_FP64) return fail(SPH_E_UNSUPPORTED, "the dual scheme runs in FP64 only");
-        if (p->use_graph) return fail(SPH_E_UNSUPPORTED, "the dual scheme does not replay graphs");
         if (!(p->cfl_adv > 0.0) || !(p->eta >= 0.0))
             return fail(SPH_E_ARG, "the dual scheme needs cfl_adv > 0 and eta >= 0");
     }
@@ -620,6 +619,10 @@ sph_status sph_create(const sph_params *p, sph_ctx **out)
     sc.cfl_adv = c->dual ? p->cfl_adv : 0.0;
     sc.cfl_sub = p->cfl_ac;
     sc.eta = c->dual ? p->eta : 0.0;
+    // the plan's ceil(Dt / dac) = ceil(cfl_adv / cfl_ac * (c0 + vmax) / max(vmax,
+    // c0 / 10)) peaks at vmax = c0 / 10, where the ratio is 11 cfl_adv / cfl_ac
+    sc.nsub_bound = c->dual ? std::max(1, (int)std::ceil(11.0 * p->cfl_adv / p->cfl_ac * (1.0 + 1e-9))) : 1;
+    if (c->dual && sc.nsub_bound > 4096) { delete c; return fail(SPH_E_ARG, "cfl_adv / cfl_ac plans more than 4096 sub-steps"); }
     sc.fh = (float)sc.h;
     sc.finv_h = (float)sc.inv_h;
     sc.fcs = (float)cs;
@@ -678,6 +681,13 @@ sph_status sph_get_info(const sph_ctx *ctx, sph_info *info)
     info->cell_size = ctx->sc.cs;
     info->steps_done = ctx->steps_done;
     info->substeps_done = ctx->substeps_done;
+    if (ctx->dual && ctx->primed) {
+        // counted on the device (the plan never reaches the host)
+        unsigned long long tot = 0;
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(&tot, ctx->dev.subs_total, sizeof(tot), hipMemcpyDeviceToHost));
+        info->substeps_done = (int64_t)tot;
+    }
     return SPH_OK;
 }
 
@@ -772,6 +782,7 @@ sph_status sph_bind(sph_ctx *c, const sph_buffers *b, void *stream)
     d.nsub = reinterpret_cast<int *>(ws + c->o_nsub);
     d.dtsub = reinterpret_cast<double *>(ws + c->o_dtsub);
     d.nsub_max = reinterpret_cast<int *>(ws + c->o_nsubmax);
+    d.subs_total = reinterpret_cast<unsigned long long *>(ws + c->o_subtot);
     d.gate = c->skin ? reinterpret_cast<int *>(ws + c->o_gate) : nullptr;
     d.disp = c->skin ? reinterpret_cast<double *>(ws + c->o_disp) : nullptr;
     d.xb = c->dual && c->skin ? reinterpret_cast<double *>(ws + c->o_xb) : nullptr;
@@ -965,19 +976,14 @@ sph_status sph_step_batched(sph_ctx *c, int32_t n_steps, void *stream)
         return SPH_OK;
     }
     hipStream_t s = as_stream(stream);
-    if (c->dual) {
-        for (int32_t it = 0; it < n_steps; ++it) {
-            TRY(dual_advection_step(c, s, c->timing));
-            c->steps_done += 1;
-        }
-        return SPH_OK;
-    }
     const bool graph = c->p.use_graph && !c->timing;
     for (int32_t it = 0; it < n_steps; ++it) {
         const bool ro = reorder_due(c);
         if (graph) {
             TRY(ensure_graph(c, ro ? 1 : 0));
             HIP_TRY(hipGraphLaunch(c->gexec[ro ? 1 : 0], s));
+        } else if (c->dual) {
+            TRY(dual_advection_step(c, ro, s, c->timing));
         } else {
             TRY(enqueue_step(c, ro, s, c->timing));
         }

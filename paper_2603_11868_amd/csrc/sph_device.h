@@ -60,6 +60,7 @@ struct SimConst {
     double kW, kF, W0;                 // W = kW t^4 (2q+1), F = kF t^3, t = 1 - q/2
     double g[3];
     double cfl_adv, cfl_sub, eta;      // dual scheme: advection and acoustic Courant numbers, limiter
+    int nsub_bound;                    // dual scheme: most acoustic sub-steps a plan can ask for
     double bcut2;                      // (2h + skin)^2: radius of the cell stencil and the list build
     double skin;                       // Verlet skin (0: cells and lists rebuilt every step)
     int reorder_every;                 // with a skin: reorder at a rebuild this many steps after the last

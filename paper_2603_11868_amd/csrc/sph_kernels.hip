@@ -420,8 +420,10 @@ __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
             const double uref = I.c0 / 10.0;
             const double Dt = sc.cfl_adv * sc.h / (vmax > uref ? vmax : uref);
             const double dac = sc.cfl_sub * sc.h / (I.c0 + vmax);
-            int ns = (int)ceil(Dt / dac);
-            ns = ns < 1 ? 1 : ns;
+            // ceil(Dt / dac) <= nsub_bound for every finite max|v| (see
+            // sph_create); a non-finite one plans one sub-step and is flagged
+            const double q = ceil(Dt / dac);
+            const int ns = !(q >= 1.0) ? 1 : (q > (double)sc.nsub_bound ? sc.nsub_bound : (int)q);
             dt[b] = Dt;
             nsub[b] = ns;
             dtsub[b] = Dt / (double)ns;
@@ -432,6 +434,19 @@ __global__ __launch_bounds__(kReduceBlock) void k_final_reduce(
         }
         if (tot[P_BAD] > 0.0) atomicOr(flags, 2u);
     }
+}
+
+// Dual scheme: add the planned sub-steps of the advection step about to run
+// (the largest count over the instances) to the running total.
+__global__ void k_count_substeps(const int *__restrict__ nsub_max, unsigned long long *__restrict__ total)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *total += (unsigned long long)*nsub_max;
+}
+
+hipError_t launch_count_substeps(const Dev &d, hipStream_t s)
+{
+    k_count_substeps<<<1, 64, 0, s>>>(d.nsub_max, d.subs_total);
+    return hipGetLastError();
 }
 
 hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s)

@@ -54,6 +54,7 @@ struct Dev {
     int *nsub;                // [B] acoustic sub-steps of the next advection step
     double *dtsub;            // [B] their size
     int *nsub_max;            // [1] max over instances
+    unsigned long long *subs_total;   // [1] sub-steps of the advection steps since the prime
     // Verlet skin (null / unused without one): gate[0] rebuild the cell table
     // and the list this step, gate[1] reorder this step, gate[2] steps since
     // the last reorder, gate[3] reduction blocks done, gate[4] builds since
@@ -103,5 +104,6 @@ hipError_t launch_skin_displacement(const SimConst &sc, const Dev &d, hipStream_
 hipError_t launch_save_build_positions(const SimConst &sc, const Dev &d, hipStream_t s);
 // Per-instance reductions of the partials -> dt, diag, flags.
 hipError_t launch_final_reduce(const SimConst &sc, const Dev &d, int prime, hipStream_t s);
+hipError_t launch_count_substeps(const Dev &d, hipStream_t s);
 
 }  // namespace sphx

@@ -146,8 +146,11 @@ def test_dual_scheme_options_are_checked(sphmod):
     p, descs = _params(sphmod, case, **base)
     ctx = sphmod.sph_create(p)
     sphmod.sph_destroy(ctx)
-    for over, status in ((dict(precision=1), "UNSUPPORTED"), (dict(use_graph=1), "UNSUPPORTED"),
-                         (dict(cfl_adv=0.0), "E_ARG"), (dict(scheme=7), "E_ARG")):
+    # graphs replay whole advection steps (the sub-step plan stays on the device)
+    p, descs = _params(sphmod, case, use_graph=1, **base)
+    sphmod.sph_destroy(sphmod.sph_create(p))
+    for over, status in ((dict(precision=1), "UNSUPPORTED"), (dict(cfl_adv=0.0), "E_ARG"),
+                         (dict(scheme=7), "E_ARG"), (dict(cfl_adv=300.0), "E_ARG")):
         p, descs = _params(sphmod, case, **dict(base, **over))
         with pytest.raises(sphmod.SphError, match=status):
             sphmod.sph_create(p)

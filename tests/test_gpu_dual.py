@@ -228,3 +228,38 @@ def test_skin_matches_no_skin_run():
     assert a.poll_errors() == 0 and b.poll_errors() == 0
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("skin_h", [0.0, 0.3])
+def test_graph_replay_equals_eager_advection_steps(skin_h):
+    """The sub-step plan stays on the device (a fixed number of sub-step
+    slots, each instance running the ones it planned), so graphs replay whole
+    advection steps; replays, with eager work and host reads in between, equal
+    eager steps bit for bit, sub-step counts included."""
+    from paper_2603_11868_amd import sph
+    case = dambreak.make_case("small_batch")
+    kw = dict(skin=skin_h * case.h)
+    eager = _sim(case, **kw)
+    graph = _sim(case, use_graph=True, **kw)
+    refs = _refs(case)
+    for s in (eager, graph):
+        s.prime()
+    total = 0
+    for rep in range(4):
+        for s in (eager, graph):
+            s.step(3)
+        he, hg = eager.host(), graph.host()
+        for k in ("x", "v", "a", "rho", "id", "perm", "count", "cell_start", "dt", "diag"):
+            assert np.array_equal(he[k], hg[k]), (rep, k)
+        assert np.array_equal(sph.sph_substeps(eager.ctx, eager.B), sph.sph_substeps(graph.ctx, graph.B))
+        ie, ig = sph.sph_get_info(eager.ctx), sph.sph_get_info(graph.ctx)
+        assert ie.substeps_done == ig.substeps_done
+    # the counted sub-steps are the reference's plans, step by step
+    for it in range(12):
+        total += max(r.dual_plan()[1] for r in refs)
+        for r in refs:
+            r.dual_step(1)
+    assert sph.sph_get_info(graph.ctx).substeps_done == total
+    assert graph.poll_errors() == 0
+    eager.close()
+    graph.close()
