@@ -182,40 +182,41 @@ SPHX_HD void density_update(double rho_old, double sigma, double m_drho, double 
 
 // ---- force -------------------------------------------------------------------
 
-// What a force pair needs of its target and of the sweep's constants (lengths
-// in the units of r).
-template <class real>
-struct ForceTarget {
-    real vi[3];
-    real rho_i, P_i, p_i, inv_rho_i2;
-    real inv_h, kF, visc_a, eps_h2, g[3];
-};
-
 // One pair of the force sweep, branch-free over fluid and wall sources (lanes
 // of a wave mix them): the wall mirror pressure is computed for every pair and
 // selected.  A wall source carries zero velocity, rho_j = rho_i and
 // p_j = max(0, p_i + rho_i g.(x_j - x_i)).  acc and aff (fluid sources only)
-// accumulate -sum (P_i + P_j + Pi_ij) F r.
+// accumulate -sum (P_i + P_j + Pi_ij) F r.  Target values: vi, rho_i, P_i,
+// p_i = P_i rho_i^2, inv_rho_i2 = 1 / rho_i^2; sweep constants (lengths in the
+// units of r): inv_h, kF, visc_a = alpha c0 h, eps_h2, g.
 template <int DIM, class real>
-SPHX_HD void force_pair(const ForceTarget<real> &T, bool wall, const real *r, real r2, const real *vj,
-                        real rho_rec, real P_rec, real *acc, real *aff, int &cnt)
+SPHX_HD void force_pair(bool wall, const real *r, real r2, const real *vi, const real *vj, real rho_i, real P_i,
+                        real p_i, real inv_rho_i2, real rho_rec, real P_rec, real inv_h, real kF, real visc_a,
+                        real eps_h2, real gx, real gy, real gz, real *acc, real *aff, int &cnt)
 {
     real F;
-    kernel_F(r2, T.inv_h, T.kF, F);
-    real vr = (T.vi[0] - vj[0]) * r[0] + (T.vi[1] - vj[1]) * r[1];
-    if constexpr (DIM == 3) vr += (T.vi[2] - vj[2]) * r[2];
-    real gr = T.g[0] * r[0] + T.g[1] * r[1];
-    if constexpr (DIM == 3) gr += T.g[2] * r[2];
-    real p_m = T.p_i - T.rho_i * gr;       // wall mirror: p_i + rho_i g.(x_j - x_i)
+    kernel_F(r2, inv_h, kF, F);
+    real vr = (vi[0] - vj[0]) * r[0] + (vi[1] - vj[1]) * r[1];
+    if constexpr (DIM == 3) vr += (vi[2] - vj[2]) * r[2];
+    real gr = gx * r[0] + gy * r[1];
+    if constexpr (DIM == 3) gr += gz * r[2];
+    real p_m = p_i - rho_i * gr;           // wall mirror: p_i + rho_i g.(x_j - x_i)
     p_m = p_m < (real)0 ? (real)0 : p_m;
-    const real rho_j = wall ? T.rho_i : rho_rec;
-    const real P_j = wall ? p_m * T.inv_rho_i2 : P_rec;
+    const real rho_j = wall ? rho_i : rho_rec;
+    const real P_j = wall ? p_m * inv_rho_i2 : P_rec;
     real visc = 0;
-    if (vr < (real)0) {
-        const real den = (real)0.5 * (T.rho_i + rho_j) * (r2 + T.eps_h2);
-        visc = -T.visc_a * vr * recip(den);
+    if constexpr (sizeof(real) == sizeof(float)) {
+        // FP32 (the mixed GPU path): branch-free, vr clamped to <= 0 (a
+        // receding pair then adds a signed zero to P_i + P_j >= +0, which
+        // leaves the sum as it is); the lanes of a wave mix approaching and
+        // receding pairs, and the hardware reciprocal is one instruction
+        const real den = (real)0.5 * (rho_i + rho_j) * (r2 + eps_h2);
+        visc = -visc_a * (vr < (real)0 ? vr : (real)0) * recip(den);
+    } else if (vr < (real)0) {
+        const real den = (real)0.5 * (rho_i + rho_j) * (r2 + eps_h2);
+        visc = -visc_a * vr * recip(den);
     }
-    const real coef = (T.P_i + P_j + visc) * F;
+    const real coef = (P_i + P_j + visc) * F;
     const real coef_ff = wall ? (real)0 : coef;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {

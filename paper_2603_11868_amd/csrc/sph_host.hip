@@ -286,21 +286,14 @@ void HostExec::force(bool fused)
         const double dtb = fused ? buf_.dt[hc.b] : 0.0;
         double *tot = vals_.data() + ci * kNPart;
         for (int64_t k = hc.begin; k < hc.end; ++k) {
-            ForceTarget<double> T;
-            double pi[3] = {0, 0, 0};
-            for (int c = 0; c < 3; ++c) {
-                pi[c] = c < DIM ? xs_[c * n + k] : 0.0;
-                T.vi[c] = c < DIM ? vs_[c * n + k] : 0.0;
-                T.g[c] = sc_.g[c];
+            double pi[3] = {0, 0, 0}, vi[3] = {0, 0, 0};
+            for (int c = 0; c < DIM; ++c) {
+                pi[c] = xs_[c * n + k];
+                vi[c] = vs_[c * n + k];
             }
-            T.rho_i = rhos_[k];
-            T.P_i = Ps_[k];
-            T.p_i = T.P_i * T.rho_i * T.rho_i;
-            T.inv_rho_i2 = 1.0 / (T.rho_i * T.rho_i);
-            T.inv_h = sc_.inv_h;
-            T.kF = sc_.kF;
-            T.visc_a = sc_.alpha * I.c0 * sc_.h;
-            T.eps_h2 = sc_.eps_h2;
+            const double rho_i = rhos_[k], P_i = Ps_[k];
+            const double p_i = P_i * rho_i * rho_i, inv_rho_i2 = 1.0 / (rho_i * rho_i);
+            const double visc_a = sc_.alpha * I.c0 * sc_.h;
             double acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
             int cnt = 0;
             host_neighbours<DIM>(sc_, I, skey_[k] - I.cell_base, k, pi, buf_.cell_start, buf_.wall_start,
@@ -313,7 +306,9 @@ void HostExec::force(bool fused)
                                          rho_j = rhos_[s];
                                          P_j = Ps_[s];
                                      }
-                                     force_pair<DIM, double>(T, wall, r, r2, vj, rho_j, P_j, acc, aff, cnt);
+                                     force_pair<DIM, double>(wall, r, r2, vi, vj, rho_i, P_i, p_i, inv_rho_i2, rho_j,
+                                                             P_j, sc_.inv_h, sc_.kF, visc_a, sc_.eps_h2, sc_.g[0],
+                                                             sc_.g[1], sc_.g[2], acc, aff, cnt);
                                  });
             const int i = buf_.perm[k];
             double vals[kNPart];

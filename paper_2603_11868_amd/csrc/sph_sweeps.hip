@@ -30,26 +30,20 @@ namespace sphx {
 // Neighbour-list entries, 32 bits: source slot in bits 0..24; on the mixed path
 // the source cell's offset from the target cell in bits 25..30 (two bits per
 // axis, offset + 1); wall flag in bit 31.
-// Skin walks: run the walk of a step without a build in a kernel of its own,
-// free of the candidate-test code and its registers.
-constexpr bool kSkinSplitWalk = true;
-// Candidate tests and list build in a kernel of their own (k_build), the
-// density walk after it: the build then runs at the occupancy of its own
-// registers, not at that of the FP64 density sums.
-constexpr bool kSplitBuild = true;
 // List walks gather records cooperatively (walk_coop).
 constexpr bool kCoopWalk = true;
 template <int DIM, bool MIXED> constexpr bool use_coop() { return kCoopWalk; }
 // List positions fetched at a time by the cooperative walks (1, 2, 4, 6 or 8;
 // six and eight read three and two quads of entries per iteration).  Measured
-// on the 2.0 M-particle 3D dam break: eight in the walk-only density kernels
-// (FP64 739 -> 630 us, mixed 500 -> 420 us) and the 3D mixed force
-// (528 -> 417 us); six in the 3D FP64 force (716 -> 673 us; eight leave two
-// waves per SIMD: 782 us); four beside the candidate tests (FP64 density
-// build 1512 -> 1660 us with eight), in the 2D forces (64-instance 2D batch:
-// mixed 554 -> 589 us with eight, FP64 795 -> 916 us with six) and in the
-// dual scheme's sweeps (six: no change; eight: 5 % slower).
-constexpr int kCoopRoundsWalk = 8, kCoopRoundsBuild = 4, kCoopRoundsDual = 4;
+// on the 2.0 M-particle 3D dam break: eight in the density walks (FP64
+// 739 -> 630 us, mixed 500 -> 420 us) and the 3D mixed force (528 -> 417 us);
+// six in the 3D FP64 force (716 -> 673 us; eight leave two waves per SIMD:
+// 782 us); four in the 2D forces (64-instance 2D batch: mixed 554 -> 589 us
+// with eight, FP64 795 -> 916 us with six) and in the dual scheme's sweeps
+// (six: no change; eight: 5 % slower).  On the 29 M-particle case, eight
+// stay best in the mixed density walk (six: +17 %, four: +29 %) and equal
+// six in the mixed force.
+constexpr int kCoopRoundsWalk = 8, kCoopRoundsDual = 4;
 template <int DIM, bool MIXED> constexpr int coop_rounds_force() { return DIM == 3 ? (MIXED ? 8 : 6) : 4; }
 // List entries in flight per lane in the per-lane walks (walk_list: every
 // walk when the cooperative gather is off).  Deep prefetch beats occupancy in these L1-bound walks: measured on
@@ -57,7 +51,6 @@ template <int DIM, bool MIXED> constexpr int coop_rounds_force() { return DIM ==
 // (FP64) were faster than 8 at 3 or 4 at 5.
 template <int DIM, bool MIXED> constexpr int skin_walk_u() { return 16; }
 template <int DIM, bool MIXED> constexpr int force_walk_u() { return MIXED && DIM == 3 ? 16 : 8; }
-template <bool MIXED> constexpr int fused_walk_u() { return MIXED ? 8 : 4; }   // after the candidate tests
 constexpr int kDualWalkU = 4;          // the sub-step sweeps of the dual scheme (FP64): 8 was slower
 
 constexpr int kSlotBits = 25;
@@ -219,7 +212,7 @@ __device__ __forceinline__ auto walk_cut2(const SimConst &sc)
 // exact fixed-point test inside its pair function (with a skin, the FP32 test
 // of the walk first skips the entries well beyond 2h).
 template <bool MIXED, int LIST>
-constexpr bool density_chk() { return !MIXED || LIST == 2 || LIST == 3; }
+constexpr bool density_chk() { return !MIXED || LIST == 3; }
 
 // How much of B a sweep needs from each fluid source.
 enum { NEED_NONE = 0, NEED_VEL = 1, NEED_ALL = 2 };
@@ -1243,7 +1236,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     if (over && lane == 0) atomicOr(flags, 4u);
 }
 
-// Candidate tests and list build alone (kSplitBuild): lists of every target
+// Candidate tests and list build (a lane per target): lists of every target
 // and their lengths (lcount); a list longer than cap raises
 // SPH_FLAG_CAPACITY (its target searches the cells in the sweeps).  SKIN:
 // with radius 2h + skin, on build steps only (*gate != 0).
@@ -1286,35 +1279,24 @@ __global__ __launch_bounds__(kMaxBlock) void k_build(
     if (m > cap) atomicOr(flags, 4u);
 }
 
-// LIST = 0: direct search.  LIST = 1: build the list, then walk it.  LIST = 2
-// (Verlet skin): build the list with radius 2h + skin when the previous
-// step's reduction asked for a rebuild (*gate != 0), else walk the list of the
-// last build; entries at 2h or beyond are skipped.  LIST = 3: that walk alone,
-// in a kernel of its own (launched after LIST = 2, or after k_build on every
-// step with kSplitBuild).  LIST = 5: the walk of a list without a skin, after
-// k_build.
-template <int DIM, bool MIXED, int LIST, int PF>
+// LIST = 0: direct search.  LIST = 5: walk the list of this step's build
+// (launch_build).  LIST = 3 (Verlet skin): walk the list of the last build,
+// skipping the entries at 2h or beyond.  A target whose list overflowed
+// searches the cells instead.
+template <int DIM, bool MIXED, int LIST>
 __global__ __launch_bounds__(kMaxBlock) void k_density(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     const int *__restrict__ skey, const int *__restrict__ perm, const int *__restrict__ cstart,
     const int *__restrict__ wstart, typename Rec<DIM, MIXED>::v4 *__restrict__ rec,
-    const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos, const typename Cand<DIM>::t *__restrict__ cpos,
-    const typename Cand<DIM>::t *__restrict__ wcpos, double *__restrict__ rho, int *__restrict__ count,
-    const double *__restrict__ dt, int use_dt, uint4 *__restrict__ nlist, int *__restrict__ lcount, int cap,
-    unsigned *__restrict__ flags, const int *__restrict__ gate)
+    const typename Rec<DIM, MIXED>::wpos_t *__restrict__ wpos, double *__restrict__ rho, int *__restrict__ count,
+    const double *__restrict__ dt, int use_dt, const uint4 *__restrict__ nlist, const int *__restrict__ lcount,
+    int cap)
 {
     using V = RV<DIM, MIXED>;
     using real = typename V::real;
     using v4 = typename V::v4;
+    static_assert(LIST == 0 || LIST == 3 || LIST == 5, "density sweeps: direct search or a list walk");
     constexpr int NEED = DIM == 3 ? NEED_VEL : NEED_NONE;
-    // split skin walks: LIST = 2 runs on build steps only, LIST = 3 (walk
-    // only) on the others
-    if constexpr (LIST == 2 && kSkinSplitWalk) {
-        if (*gate == 0) return;
-    }
-    if constexpr (LIST == 3 && !kSplitBuild) {
-        if (*gate != 0) return;
-    }
     // the cooperative walk needs every lane of the wave, targets or not
     constexpr bool COOP = LIST != 0 && use_coop<DIM, MIXED>();
     const Chunk ch = map[blockIdx.x];
@@ -1371,55 +1353,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
         walk_coop<DIM, MIXED, NEED, density_chk<MIXED, LIST>(), kCoopRoundsWalk>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
         if (act && m > cap) for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
         if (!act) return;
-    } else if constexpr (COOP) {
-        // candidate tests per target, then the cooperative walk with every lane
-        const bool build = LIST == 1 || *gate != 0;
-        int m = 0;
-        if (act) {
-            if (build) {
-                float ci[3];
-                const typename Cand<DIM>::t cp = cpos[k];
-                ci[0] = cp.x; ci[1] = cp.y;
-                if constexpr (DIM == 3) ci[2] = cp.z;
-                else ci[2] = 0.0f;
-                m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
-                                               nlist, cap, n);
-                lcount[k] = m;
-            } else {
-                m = lcount[k];
-            }
-        }
-        walk_coop<DIM, MIXED, NEED, density_chk<MIXED, LIST>(), kCoopRoundsBuild>(sc, kk, m <= cap ? m : 0, pi, rec, nlist, n, cut2, pair);
-        if (act && m > cap) {
-            if (build) atomicOr(flags, 4u);
-            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
-        }
-        if (!act) return;
     } else if constexpr (LIST == 3 || LIST == 5) {
         const int m = lcount[k];
         if (m <= cap) walk_list<DIM, MIXED, skin_walk_u<DIM, MIXED>(), NEED, density_chk<MIXED, LIST>()>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
         else for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
-    } else if constexpr (LIST) {
-        float ci[3];
-        const typename Cand<DIM>::t cp = cpos[k];
-        ci[0] = cp.x; ci[1] = cp.y;
-        if constexpr (DIM == 3) ci[2] = cp.z;
-        else ci[2] = 0.0f;
-        const bool build = LIST == 1 || *gate != 0;
-        int m;
-        if (build) {
-            m = build_list<DIM, MIXED, PF>(sc, I, lk, k, pi, ci, cstart, wstart, rec, wpos, cpos, wcpos,
-                                           nlist, cap, n);
-            lcount[k] = m;
-        } else {
-            m = lcount[k];
-        }
-        if (m <= cap) {
-            walk_list<DIM, MIXED, fused_walk_u<MIXED>(), NEED, density_chk<MIXED, LIST>()>(sc, k, m, pi, rec, wpos, nlist, n, cut2, pair);
-        } else {
-            if (build) atomicOr(flags, 4u);
-            for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
-        }
     } else {
         for_neighbours<DIM, MIXED, NEED>(sc, I, lk, k, pi, cstart, wstart, rec, wpos, cut2, pair);
     }
@@ -1438,15 +1375,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_density(
     reinterpret_cast<typename V::v2 *>(rec)[V::rhoP_slot(k)] = out;
 }
 
-template <int DIM, bool MIXED, int LIST, int PF>
+template <int DIM, bool MIXED, int LIST>
 static void density_dispatch(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
 {
     using R = Rec<DIM, MIXED>;
-    k_density<DIM, MIXED, LIST, PF><<<d.nfchunks, d.block, 0, s>>>(
+    k_density<DIM, MIXED, LIST><<<d.nfchunks, d.block, 0, s>>>(
         sc, d.fmap, d.inst, d.skey, d.perm, d.cell_start, d.wall_start, static_cast<typename R::v4 *>(d.rec),
-        static_cast<const typename R::wpos_t *>(d.wpos), static_cast<const typename Cand<DIM>::t *>(d.cpos),
-        static_cast<const typename Cand<DIM>::t *>(d.wcpos), d.rho, d.count, d.dt, use_dt, d.nlist, d.lcount,
-        d.list_cap, d.flags, d.gate);
+        static_cast<const typename R::wpos_t *>(d.wpos), d.rho, d.count, d.dt, use_dt, d.nlist, d.lcount,
+        d.list_cap);
 }
 
 template <int DIM, bool MIXED, bool SKIN, int PF>
@@ -1489,7 +1425,7 @@ static void build_variant(const SimConst &sc, const Dev &d, hipStream_t s)
 
 hipError_t launch_build(const SimConst &sc, const Dev &d, int mixed, hipStream_t s)
 {
-    if (d.nfchunks <= 0 || d.list_cap <= 0 || !kSplitBuild) return hipSuccess;
+    if (d.nfchunks <= 0 || d.list_cap <= 0) return hipSuccess;
     if (sc.dim == 2) { if (mixed) build_variant<2, true>(sc, d, s); else build_variant<2, false>(sc, d, s); }
     else { if (mixed) build_variant<3, true>(sc, d, s); else build_variant<3, false>(sc, d, s); }
     return hipGetLastError();
@@ -1498,17 +1434,10 @@ hipError_t launch_build(const SimConst &sc, const Dev &d, int mixed, hipStream_t
 template <int DIM, bool MIXED>
 static void density_variant(const SimConst &sc, const Dev &d, int use_dt, hipStream_t s)
 {
-    if (d.list_cap <= 0) density_dispatch<DIM, MIXED, 0, 4>(sc, d, use_dt, s);
-    else if (kSplitBuild) {
-        // the lists come from launch_build
-        if (d.gate) density_dispatch<DIM, MIXED, 3, 4>(sc, d, use_dt, s);
-        else density_dispatch<DIM, MIXED, 5, 4>(sc, d, use_dt, s);
-    } else if (d.gate) {
-        if (d.prefetch == 4) density_dispatch<DIM, MIXED, 2, 4>(sc, d, use_dt, s);
-        else density_dispatch<DIM, MIXED, 2, 8>(sc, d, use_dt, s);
-        if (kSkinSplitWalk) density_dispatch<DIM, MIXED, 3, 4>(sc, d, use_dt, s);
-    } else if (d.prefetch == 4) density_dispatch<DIM, MIXED, 1, 4>(sc, d, use_dt, s);
-    else density_dispatch<DIM, MIXED, 1, 8>(sc, d, use_dt, s);
+    // the lists come from launch_build
+    if (d.list_cap <= 0) density_dispatch<DIM, MIXED, 0>(sc, d, use_dt, s);
+    else if (d.gate) density_dispatch<DIM, MIXED, 3>(sc, d, use_dt, s);
+    else density_dispatch<DIM, MIXED, 5>(sc, d, use_dt, s);
 }
 
 hipError_t launch_density(const SimConst &sc, const Dev &d, int mixed, int use_dt, hipStream_t s)
@@ -1562,28 +1491,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_force(
     const real gy = MIXED ? (real)sc.ug[1] : (real)sc.g[1];
     const real gz = MIXED ? (real)sc.ug[2] : (real)sc.g[2];
     const real cut2 = walk_cut2<MIXED>(sc);
-    ForceTarget<real> T;
-    T.vi[0] = vi[0];
-    T.vi[1] = vi[1];
-    T.vi[2] = vi[2];
-    T.rho_i = rho_i;
-    T.P_i = P_i;
-    T.p_i = p_i;
-    T.inv_rho_i2 = inv_rho_i2;
-    T.inv_h = inv_h;
-    T.kF = kF;
-    T.visc_a = visc_a;
-    T.eps_h2 = eps_h2;
-    T.g[0] = gx;
-    T.g[1] = gy;
-    T.g[2] = gz;
     real acc[3] = {0, 0, 0}, aff[3] = {0, 0, 0};
     int cnt = 0;
     auto pair = [&](bool wall, int, const real *r, real r2, const v4 &Aj, const v4 &Bj, unsigned)
         __attribute__((always_inline)) {
         real vj[3];
         V::vel(Aj, Bj, vj);                // zero for walls
-        force_pair<DIM, real>(T, wall, r, r2, vj, V::rho(Bj), V::P(Bj), acc, aff, cnt);
+        force_pair<DIM, real>(wall, r, r2, vi, vj, rho_i, P_i, p_i, inv_rho_i2, V::rho(Bj), V::P(Bj), inv_h, kF,
+                              visc_a, eps_h2, gx, gy, gz, acc, aff, cnt);
     };
     if constexpr (LIST && use_coop<DIM, MIXED>()) {
         // every lane takes part in the cooperative walk
