@@ -1101,17 +1101,12 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
 
     // list output, one target behind: the quads of the last target are read
     // from the staging before the next target's tests write it (a wave's LDS
-    // operations execute in order) and stored after them
+    // operations execute in order) and stored after them.  Entries of the
+    // last quad past the list length are stored as the staging holds them:
+    // the walks never read past it.
     int pend_t = -1, pend_mm = 0;
     auto store_pending = [&](const uint4 &o) __attribute__((always_inline)) {
-        if (pend_t >= 0 && lane < ((pend_mm + 3) >> 2)) {
-            const int b = 4 * lane;
-            uint4 q = o;
-            q.y = b + 1 < pend_mm ? q.y : 0u;
-            q.z = b + 2 < pend_mm ? q.z : 0u;
-            q.w = b + 3 < pend_mm ? q.w : 0u;
-            nlist[(int64_t)lane * n + pend_t] = q;
-        }
+        if (pend_t >= 0 && lane < ((pend_mm + 3) >> 2)) nlist[(int64_t)lane * n + pend_t] = o;
     };
 
     Ranges R = ranges(__builtin_amdgcn_readlane(lkl, 0));
