@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     const int kup = lane_value(kl, lane > 0 ? lane - 1 : 0);
     uint64_t starts = __builtin_amdgcn_ballot_w64(tv && (lane == 0 || kl != kup));
     int lc = -1;                                          // list length of the lane's target (-1: k_build)
-    bool over = false;                                    // a list longer than cap
+    int mmax = 0;                                         // the longest list of the wave
 
     // the cell of the lane's target (instance-local key)
     const int lkl = kl - I.cell_base;
@@ -1169,45 +1169,45 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
         // chunks past nch never hit): one unrolled copy per chunk count
         auto targets = [&](auto ncc) __attribute__((always_inline)) {
             constexpr int NC = decltype(ncc)::value;
-            for (int l = a; l < b; ++l) {
+            // the cell's targets a..b-1 without the far ones (left to k_build)
+            uint64_t todo = (b - a >= 64 ? ~0ull : ((1ull << (b - a)) - 1ull)) << a;
+            todo &= ~farm;
+            while (todo) {
+                const int l = (int)__builtin_ctzll(todo);
+                todo &= todo - 1ull;
                 const uint4 o = reinterpret_cast<const uint4 *>(lst)[lane];   // the pending quads
-                const bool skip = (farm >> l) & 1ull;
+                const float ttx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(txl), l));
+                const float tty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tyl), l));
+                float ttz = 0.0f;
+                if constexpr (DIM == 3) ttz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tzl), l));
+                const float ct = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ctl), l));
+                // the target's own entry, the one source that is not a pair
+                unsigned eself = (unsigned)(w0 + l) | (MIXED ? offset_bits(0, 0, 0) : 0u);
+                // an opaque scalar: no induction variable per chunk
+                asm volatile("" : "+s"(eself));
                 unsigned *lp = lst;                       // the target's next list place
-                if (!skip) {
-                    const float ttx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(txl), l));
-                    const float tty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tyl), l));
-                    float ttz = 0.0f;
-                    if constexpr (DIM == 3) ttz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tzl), l));
-                    const float ct = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ctl), l));
-                    // the target's own entry, the one source that is not a pair
-                    unsigned eself = (unsigned)(w0 + l) | (MIXED ? offset_bits(0, 0, 0) : 0u);
-                    // an opaque scalar: no induction variable per chunk
-                    asm volatile("" : "+s"(eself));
 #pragma unroll
-                    for (int j = 0; j < NC; ++j) {
-                        float d = fmaf(qx[j], ttx, pp[j]);
-                        d = fmaf(qy[j], tty, d);
-                        if constexpr (DIM == 3) d = fmaf(qz[j], ttz, d);
-                        const bool near = d < ct, other = ent[j] != eself;
-                        const uint64_t hm = __builtin_amdgcn_ballot_w64(near) & __builtin_amdgcn_ballot_w64(other);
-                        int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
-                        // every lane writes: a hit at its place in the list, any
-                        // other lane past the places this chunk's hits can take
-                        // (later hits overwrite it, or it lies past the list)
-                        asm volatile("" : "+v"(pos));
-                        lp[near && other ? pos : 64 + lane] = ent[j];
-                        lp += __popcll(hm);
-                    }
+                for (int j = 0; j < NC; ++j) {
+                    float d = fmaf(qx[j], ttx, pp[j]);
+                    d = fmaf(qy[j], tty, d);
+                    if constexpr (DIM == 3) d = fmaf(qz[j], ttz, d);
+                    const bool near = d < ct, other = ent[j] != eself;
+                    const uint64_t hm = __builtin_amdgcn_ballot_w64(near) & __builtin_amdgcn_ballot_w64(other);
+                    int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
+                    // every lane writes: a hit at its place in the list, any
+                    // other lane past the places this chunk's hits can take
+                    // (later hits overwrite it, or it lies past the list)
+                    asm volatile("" : "+v"(pos));
+                    lp[near && other ? pos : 64 + lane] = ent[j];
+                    lp += __popcll(hm);
                 }
                 const int m = (int)(lp - lst);
                 store_pending(o);
-                pend_t = skip ? -1 : w0 + l;
+                pend_t = w0 + l;
                 pend_mm = min(m, cap);
-                if (!skip) {
-                    lc = lane == l ? m : lc;
-                    over |= m > cap;
-                }
+                lc = lane == l ? m : lc;
+                mmax = max(mmax, m);
             }
         };
         using std::integral_constant;
@@ -1228,7 +1228,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     }
     store_pending(reinterpret_cast<const uint4 *>(lst)[lane]);
     if (tv) lcount[w0 + lane] = lc;
-    if (over && lane == 0) atomicOr(flags, 4u);
+    if (mmax > cap && lane == 0) atomicOr(flags, 4u);
 }
 
 // Candidate tests and list build (a lane per target): lists of every target
