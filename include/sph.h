@@ -300,8 +300,10 @@ sph_status sph_sort(sph_ctx *ctx, int32_t reorder, void *stream);
  * list_cap.) */
 sph_status sph_density(sph_ctx *ctx, void *stream);
 
-/* Force sweep: a (storage order).  Does not kick.  (Sec. 5: the pairs of
- * the nearest cells; Sec. 4: a particle_for.) */
+/* Force sweep: a (storage order).  Does not kick.  Reads the densities and
+ * pressures that sph_density writes into the sweep records, so it follows
+ * sph_density (sph_sort leaves those record fields zero).  (Sec. 5: the
+ * pairs of the nearest cells; Sec. 4: a particle_for.) */
 sph_status sph_forces(sph_ctx *ctx, void *stream);
 
 /* half = 1: v += dt/2 a, x += dt v, then cell keys as sph_build_cells.

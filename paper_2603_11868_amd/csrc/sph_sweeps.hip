@@ -362,17 +362,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack(
         if constexpr (MIXED) p[c] = qfix(od[c], sc.cs, sc.inv_cs);
         else p[c] = xi[c];
     }
-    typename V::v4 A;
+    // whole records: (rho, P) get zeros here and their values from the density
+    // sweep, which runs before anything reads them; writing every byte of the
+    // record's sectors spares the memory a read-modify-write of partial ones
+    typename V::v4 A, B{};
     if constexpr (DIM == 3) {
         A.x = p[0]; A.y = p[1]; A.z = p[2]; A.w = (real)vi[0];
-        typename V::v2 Bv;
-        Bv.x = (real)vi[1];
-        Bv.y = (real)vi[2];
-        reinterpret_cast<typename V::v2 *>(rec)[4 * (int64_t)k + 2] = Bv;
+        B.x = (real)vi[1];
+        B.y = (real)vi[2];
     } else {
         A.x = p[0]; A.y = p[1]; A.z = (real)vi[0]; A.w = (real)vi[1];
     }
     rec[2 * (int64_t)k] = A;
+    rec[2 * (int64_t)k + 1] = B;
     // the FP32 copies serve the candidate tests, which only a build runs
     if (gate == nullptr || *gate != 0) {
         typename Cand<DIM>::t cp;
