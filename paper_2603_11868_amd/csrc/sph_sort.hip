@@ -123,6 +123,15 @@ __device__ __forceinline__ uint64_t match_digit(unsigned d, bool valid)
     return m;
 }
 
+// Tile of block b: blocks go to the 8 XCDs round robin, and each XCD takes a
+// contiguous range of tiles, so that the runs neighbouring tiles write for a
+// digit (which share memory sectors at their ends) meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nt)
+{
+    const int per = nt >> 3, rem = nt & 7, x = b & 7;
+    return x * per + min(x, rem) + (b >> 3);
+}
+
 __global__ __launch_bounds__(RS_BS) void k_radix_hist(const int *__restrict__ keys, int n,
                                                       int shift, int *__restrict__ hist,
                                                       int ntiles, const int *__restrict__ gate)
@@ -132,7 +141,8 @@ __global__ __launch_bounds__(RS_BS) void k_radix_hist(const int *__restrict__ ke
     const int tid = threadIdx.x;
     h[tid] = 0;
     __syncthreads();
-    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int64_t tbase = (int64_t)tile * RS_TILE;
     for (int r = 0; r < RS_IPT; ++r) {
         const int64_t idx = tbase + r * RS_BS + tid;
         const bool valid = idx < n;
@@ -141,7 +151,7 @@ __global__ __launch_bounds__(RS_BS) void k_radix_hist(const int *__restrict__ ke
         if (valid && mbcnt(m) == 0) atomicAdd(&h[d], (int)__popcll(m));
     }
     __syncthreads();
-    hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+    hist[(int64_t)tid * ntiles + tile] = h[tid];
 }
 
 __global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__ kin,
@@ -157,11 +167,12 @@ __global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__
     __shared__ int wc[RS_BS / 64][RS_RADIX];
     const int tid = threadIdx.x;
     const int w = tid >> 6;
-    base[tid] = hist[(int64_t)tid * ntiles + blockIdx.x];
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    base[tid] = hist[(int64_t)tid * ntiles + tile];
 #pragma unroll
     for (int q = 0; q < RS_BS / 64; ++q) wc[q][tid] = 0;
     __syncthreads();
-    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tbase = (int64_t)tile * RS_TILE;
     for (int r = 0; r < RS_IPT; ++r) {
         const int64_t idx = tbase + r * RS_BS + tid;
         const bool valid = idx < n;
