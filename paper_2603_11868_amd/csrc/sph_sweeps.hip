@@ -1633,10 +1633,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_first(
     rho[i] = r;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) x[(int64_t)c * n + i] = half_update(x[(int64_t)c * n + i], v[(int64_t)c * n + i], dt);
-    dvec2 rp;
-    rp.x = r;
-    rp.y = p;
-    reinterpret_cast<dvec2 *>(rec)[V::rhoP_slot(k)] = rp;
+    // (rho, p) go into the record with the whole 32-byte half around them (3D:
+    // the velocities as held; 2D: padding), so no sector is written in part
+    typename V::v4 B{};
+    if constexpr (DIM == 3) {
+        B = rec[2 * (int64_t)k + 1];
+        B.z = r;
+        B.w = p;
+    } else {
+        B.x = r;
+        B.y = p;
+    }
+    rec[2 * (int64_t)k + 1] = B;
 }
 
 // Second half (sorted order): half drift with the new velocity, and the new
@@ -1660,15 +1668,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_dual_second(
         vi[c] = v[(int64_t)c * n + i];
         x[(int64_t)c * n + i] = half_update(x[(int64_t)c * n + i], vi[c], dt);
     }
-    double *A = reinterpret_cast<double *>(rec + 2 * (int64_t)k);
+    // the velocities go into the record with the whole 32-byte halves around
+    // them (positions, (rho, p) as held), so no sector is written in part
+    typename Rec<DIM, false>::v4 A = rec[2 * (int64_t)k];
     if constexpr (DIM == 3) {
-        A[3] = vi[0];                      // A.w
-        A[4] = vi[1];                      // B.x
-        A[5] = vi[2];                      // B.y
+        typename Rec<DIM, false>::v4 B = rec[2 * (int64_t)k + 1];
+        A.w = vi[0];
+        B.x = vi[1];
+        B.y = vi[2];
+        rec[2 * (int64_t)k + 1] = B;
     } else {
-        A[2] = vi[0];                      // A.z
-        A[3] = vi[1];                      // A.w
+        A.z = vi[0];
+        A.w = vi[1];
     }
+    rec[2 * (int64_t)k] = A;
 }
 
 // Pair state shared by both sweeps.
