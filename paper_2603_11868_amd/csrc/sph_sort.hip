@@ -4,10 +4,13 @@
 // 8-bit digits, least significant first, ceil(bits(C-1)/8) passes.  Each pass
 // is reduce-then-scan: per-tile digit histograms, one exclusive scan of the
 // digit-major histogram table, then a scatter in which every tile ranks its
-// keys stably.  Ranking inside a wave uses 8 ballots to find the lanes that
-// share a digit and v_mbcnt for the rank among them; across the 4 waves of a
-// block and the 16 rounds of a tile, per-digit counters in LDS keep the order
-// of the input.  Ties therefore keep their input order, and the result is the
+// keys stably.  Ranking inside a wave: where the wave's digits do not
+// decrease from lane to lane (keys nearly in cell order, as they are between
+// physical reorders), equal digits form one run, and a lane's rank is its
+// distance from the head of its run; otherwise 8 ballots find the lanes that
+// share a digit and v_mbcnt gives the rank among them.  Across the 4 waves of
+// a block and the 16 rounds of a tile, per-digit counters in LDS keep the
+// order of the input.  Ties therefore keep their input order, and the result is the
 // unique stable permutation: identical to a plain counting sort of the keys.
 #include "sph_launch.h"
 
@@ -123,6 +126,32 @@ __device__ __forceinline__ uint64_t match_digit(unsigned d, bool valid)
     return m;
 }
 
+// Rank of this lane among the valid lanes of the wave with its digit d (those
+// below it), and their number (valid lanes form a prefix of the wave).
+struct DigitRank { int rk, cnt; };
+__device__ __forceinline__ DigitRank digit_rank(unsigned d, bool valid)
+{
+    const int lane = lane_id();
+    const unsigned dp = (unsigned)__builtin_amdgcn_ds_bpermute((lane > 0 ? lane - 1 : 0) << 2, (int)d);
+    const int nvalid = __popcll(__ballot(valid));        // taken by every lane, before any branch
+    DigitRank o;
+    if (__ballot(valid && lane > 0 && d < dp) == 0) {
+        // non-decreasing digits: runs of equal digits, one per digit
+        const uint64_t heads = __ballot(valid && (lane == 0 || d != dp));
+        const uint64_t upto = (2ull << lane) - 1ull;      // lanes 0..lane
+        const uint64_t below = heads & upto, above = heads & ~upto;
+        const int hl = 63 - __clzll(below | 1ull);
+        const int nh = above ? __ffsll((long long)above) - 1 : nvalid;
+        o.rk = lane - hl;
+        o.cnt = nh - hl;
+    } else {
+        const uint64_t m = match_digit(d, valid);
+        o.rk = mbcnt(m);
+        o.cnt = __popcll(m);
+    }
+    return o;
+}
+
 // Tile of block b: blocks go to the 8 XCDs round robin, and each XCD takes a
 // contiguous range of tiles, so that the runs neighbouring tiles write for a
 // digit (which share memory sectors at their ends) meet in one L2.
@@ -147,8 +176,8 @@ __global__ __launch_bounds__(RS_BS) void k_radix_hist(const int *__restrict__ ke
         const int64_t idx = tbase + r * RS_BS + tid;
         const bool valid = idx < n;
         const unsigned d = valid ? ((unsigned)keys[idx] >> shift) & 255u : 0u;
-        const uint64_t m = match_digit(d, valid);
-        if (valid && mbcnt(m) == 0) atomicAdd(&h[d], (int)__popcll(m));
+        const DigitRank g = digit_rank(d, valid);
+        if (valid && g.rk == 0) atomicAdd(&h[d], g.cnt);
     }
     __syncthreads();
     hist[(int64_t)tid * ntiles + tile] = h[tid];
@@ -179,9 +208,9 @@ __global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__
         const int key = valid ? kin[idx] : 0;
         const int val = valid ? (vin ? vin[idx] : (int)idx) : 0;
         const unsigned d = ((unsigned)key >> shift) & 255u;
-        const uint64_t m = match_digit(d, valid);
-        const int rk = mbcnt(m);
-        if (valid && rk == 0) wc[w][d] = (int)__popcll(m);
+        const DigitRank g = digit_rank(d, valid);
+        const int rk = g.rk;
+        if (valid && rk == 0) wc[w][d] = g.cnt;
         __syncthreads();
         int pos = 0;
         if (valid) {
