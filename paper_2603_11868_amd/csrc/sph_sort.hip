@@ -172,10 +172,16 @@ __global__ __launch_bounds__(RS_BS) void k_radix_hist(const int *__restrict__ ke
     __syncthreads();
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int64_t tbase = (int64_t)tile * RS_TILE;
+    // the tile's digits: every load issued before the first is used (a
+    // place past the end reads the last key and is not counted)
+    unsigned dk[RS_IPT];
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r)
+        dk[r] = ((unsigned)keys[min(tbase + r * RS_BS + tid, (int64_t)n - 1)] >> shift) & 255u;
+#pragma unroll
     for (int r = 0; r < RS_IPT; ++r) {
-        const int64_t idx = tbase + r * RS_BS + tid;
-        const bool valid = idx < n;
-        const unsigned d = valid ? ((unsigned)keys[idx] >> shift) & 255u : 0u;
+        const bool valid = tbase + r * RS_BS + tid < n;
+        const unsigned d = valid ? dk[r] : 0u;
         const DigitRank g = digit_rank(d, valid);
         if (valid && g.rk == 0) atomicAdd(&h[d], g.cnt);
     }
@@ -202,11 +208,22 @@ __global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__
     for (int q = 0; q < RS_BS / 64; ++q) wc[q][tid] = 0;
     __syncthreads();
     const int64_t tbase = (int64_t)tile * RS_TILE;
+    // the tile's keys and values, loaded before the first round (places past
+    // the end read the last element and are not written)
+    int kk[RS_IPT], vv[RS_IPT];
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int64_t idx = tbase + r * RS_BS + tid;
+        const int64_t ic = min(idx, (int64_t)n - 1);
+        kk[r] = kin[ic];
+        vv[r] = vin ? vin[ic] : (int)idx;
+    }
+#pragma unroll
     for (int r = 0; r < RS_IPT; ++r) {
         const int64_t idx = tbase + r * RS_BS + tid;
         const bool valid = idx < n;
-        const int key = valid ? kin[idx] : 0;
-        const int val = valid ? (vin ? vin[idx] : (int)idx) : 0;
+        const int key = valid ? kk[r] : 0;
+        const int val = vv[r];
         const unsigned d = ((unsigned)key >> shift) & 255u;
         const DigitRank g = digit_rank(d, valid);
         const int rk = g.rk;
