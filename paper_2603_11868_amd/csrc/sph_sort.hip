@@ -31,18 +31,36 @@ int scan_tiles(int64_t n) { return (int)((n + SCAN_TILE - 1) / SCAN_TILE); }
 int64_t scan_max_elems() { return (int64_t)SCAN_TOP_BS * SCAN_TOP_IPT * SCAN_TILE; }
 int radix_tiles(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
 
+// The SCAN_IPT consecutive ints of thread t of the block: two 16-byte loads
+// where the array is 16-byte aligned and the run lies inside it, else one by
+// one (zeros past the end).
+template <bool VEC>
+__device__ __forceinline__ void scan_load(const int *__restrict__ in, int64_t base, int n, int (&v)[SCAN_IPT])
+{
+    static_assert(SCAN_IPT == 8, "two int4 per thread");
+    if (VEC && base + SCAN_IPT <= n) {
+        const int4 a = *reinterpret_cast<const int4 *>(in + base);
+        const int4 b = *reinterpret_cast<const int4 *>(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_IPT; ++j) v[j] = base + j < n ? in[base + j] : 0;
+    }
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(SCAN_BS) void k_scan_reduce(const int *__restrict__ in, int n,
                                                          int *__restrict__ part, const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
     __shared__ int lds[SCAN_BS / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int v[SCAN_IPT];
+    scan_load<VEC>(in, base, n, v);
     int s = 0;
 #pragma unroll
-    for (int j = 0; j < SCAN_IPT; ++j) {
-        int64_t idx = base + j;
-        if (idx < n) s += in[idx];
-    }
+    for (int j = 0; j < SCAN_IPT; ++j) s += v[j];
     int tot;
     block_exclusive_scan(s, lds, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -72,6 +90,7 @@ __global__ __launch_bounds__(SCAN_TOP_BS) void k_scan_top(int *__restrict__ part
     }
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(SCAN_BS) void k_scan_apply(int *__restrict__ in, int *__restrict__ out,
                                                         int n, const int *__restrict__ part,
                                                         int zero_in, const int *__restrict__ gate)
@@ -80,23 +99,33 @@ __global__ __launch_bounds__(SCAN_BS) void k_scan_apply(int *__restrict__ in, in
     __shared__ int lds[SCAN_BS / 64 + 1];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
     int v[SCAN_IPT];
+    scan_load<VEC>(in, base, n, v);
     int s = 0;
 #pragma unroll
-    for (int j = 0; j < SCAN_IPT; ++j) {
-        int64_t idx = base + j;
-        v[j] = (idx < n) ? in[idx] : 0;
-        s += v[j];
-    }
+    for (int j = 0; j < SCAN_IPT; ++j) s += v[j];
     int tot;
     int off = block_exclusive_scan(s, lds, &tot) + part[blockIdx.x];
+    int o[SCAN_IPT];
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
-        int64_t idx = base + j;
-        if (idx < n) {
-            out[idx] = off;
-            if (zero_in) in[idx] = 0;
-        }
+        o[j] = off;
         off += v[j];
+    }
+    if (VEC && base + SCAN_IPT <= n) {
+        *reinterpret_cast<int4 *>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<int4 *>(out + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+        if (zero_in) {
+            *reinterpret_cast<int4 *>(in + base) = make_int4(0, 0, 0, 0);
+            *reinterpret_cast<int4 *>(in + base + 4) = make_int4(0, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_IPT; ++j) {
+            if (base + j < n) {
+                out[base + j] = o[j];
+                if (zero_in) in[base + j] = 0;
+            }
+        }
     }
 }
 
@@ -107,9 +136,12 @@ hipError_t launch_exclusive_scan(int *in, int *out, int64_t n, int *part, int ze
     if (n <= 0) return hipSuccess;
     if (n > scan_max_elems()) return hipErrorInvalidValue;
     int nt = scan_tiles(n);
-    k_scan_reduce<<<nt, SCAN_BS, 0, s>>>(in, (int)n, part, gate);
+    const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
+    if (vec) k_scan_reduce<true><<<nt, SCAN_BS, 0, s>>>(in, (int)n, part, gate);
+    else k_scan_reduce<false><<<nt, SCAN_BS, 0, s>>>(in, (int)n, part, gate);
     k_scan_top<<<1, SCAN_TOP_BS, 0, s>>>(part, nt, gate);
-    k_scan_apply<<<nt, SCAN_BS, 0, s>>>(in, out, (int)n, part, zero_in, gate);
+    if (vec) k_scan_apply<true><<<nt, SCAN_BS, 0, s>>>(in, out, (int)n, part, zero_in, gate);
+    else k_scan_apply<false><<<nt, SCAN_BS, 0, s>>>(in, out, (int)n, part, zero_in, gate);
     return hipGetLastError();
 }
 
