@@ -230,15 +230,21 @@ __global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__
                                                          const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
-    __shared__ int base[RS_RADIX];
-    __shared__ int wc[RS_BS / 64][RS_RADIX];
+    // Per-digit offsets (two copies: round r reads copy r & 1 and writes the
+    // other) and per-wave digit counts (three copies: round r writes copy
+    // r % 3 and clears the copy of round r - 1, whose reads all came before
+    // this round's barrier and whose next writes come after the next one), so
+    // that one barrier per round orders everything.
+    __shared__ int base[2][RS_RADIX];
+    __shared__ int wc[3][RS_BS / 64][RS_RADIX];
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int tile = xcd_tile(blockIdx.x, ntiles);
-    base[tid] = hist[(int64_t)tid * ntiles + tile];
+    base[0][tid] = hist[(int64_t)tid * ntiles + tile];
 #pragma unroll
-    for (int q = 0; q < RS_BS / 64; ++q) wc[q][tid] = 0;
-    __syncthreads();
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < RS_BS / 64; ++q) wc[c][q][tid] = 0;
     const int64_t tbase = (int64_t)tile * RS_TILE;
     // the tile's keys and values, loaded before the first round (places past
     // the end read the last element and are not written)
@@ -250,35 +256,34 @@ __global__ __launch_bounds__(RS_BS) void k_radix_scatter(const int *__restrict__
         kk[r] = kin[ic];
         vv[r] = vin ? vin[ic] : (int)idx;
     }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < RS_IPT; ++r) {
+        const int cb = r & 1, cw = r % 3, cprev = (r + 2) % 3;
         const int64_t idx = tbase + r * RS_BS + tid;
         const bool valid = idx < n;
         const int key = valid ? kk[r] : 0;
-        const int val = vv[r];
         const unsigned d = ((unsigned)key >> shift) & 255u;
         const DigitRank g = digit_rank(d, valid);
-        const int rk = g.rk;
-        if (valid && rk == 0) wc[w][d] = g.cnt;
+        if (valid && g.rk == 0) wc[cw][w][d] = g.cnt;
         __syncthreads();
         int pos = 0;
         if (valid) {
-            pos = base[d] + rk;
-            for (int q = 0; q < w; ++q) pos += wc[q][d];
+            pos = base[cb][d] + g.rk;
+#pragma unroll
+            for (int q = 0; q < RS_BS / 64; ++q) pos += q < w ? wc[cw][q][d] : 0;
         }
-        __syncthreads();
         int add = 0;
 #pragma unroll
         for (int q = 0; q < RS_BS / 64; ++q) {
-            add += wc[q][tid];
-            wc[q][tid] = 0;
+            add += wc[cw][q][tid];
+            wc[cprev][q][tid] = 0;
         }
-        base[tid] += add;
+        base[cb ^ 1][tid] = base[cb][tid] + add;
         if (valid) {
             kout[pos] = key;
-            vout[pos] = val;
+            vout[pos] = vv[r];
         }
-        __syncthreads();
     }
 }
 
