@@ -679,19 +679,19 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
     uint4 buf = make_uint4(0u, 0u, 0u, 0u);
     const int dz_lo = (DIM == 3 && c.cz > 0) ? -1 : 0;
     const int dz_hi = (DIM == 3 && c.cz < ncz - 1) ? 1 : 0;
-    for (int dz = dz_lo; dz <= dz_hi; ++dz) {
-        for (int dy = -1; dy <= 1; ++dy) {
+    // the fluid (PASS 0) or wall (PASS 1) slots of stencil row (dy, dz)
+    auto row = [&](int dz, int dy, auto passc) __attribute__((always_inline)) {
+            constexpr int pass = decltype(passc)::value;
             const int yy = c.cy + dy;
-            if (yy < 0 || yy >= ncy) continue;
+            if (yy < 0 || yy >= ncy) return;
             int xlo, xhi;
-            if (!row_cells(o, cs, cut2m, dy, dz, c.cx, ncx, xlo, xhi)) continue;
+            if (!row_cells(o, cs, cut2m, dy, dz, c.cx, ncx, xlo, xhi)) return;
             // a needed row is scanned whole: targets of one cell then read the
             // same candidates at the same time, one cache line for all of them
             xlo = c.cx > 0 ? c.cx - 1 : c.cx;
             xhi = c.cx < ncx - 1 ? c.cx + 1 : c.cx;
             const int nseg = row_segments(sc, xlo, xhi);
-#pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
+            {
                 const int *__restrict__ st = pass == 0 ? cstart : wstart;
                 const unsigned wall_bit = pass == 1 ? kWallBit : 0u;
               for (int g = 0; g < nseg; ++g) {
@@ -743,6 +743,16 @@ __device__ __forceinline__ int build_list(const SimConst &sc, const InstDev &I, 
                 }
               }
             }
+    };
+    // the centre row's fluid first (it holds the target's own cell), then the
+    // other rows in z, y order, fluid then wall slots: the order of the
+    // cell-pair build's sequence
+    using std::integral_constant;
+    row(0, 0, integral_constant<int, 0>{});
+    for (int dz = dz_lo; dz <= dz_hi; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            if (dz != 0 || dy != 0) row(dz, dy, integral_constant<int, 0>{});
+            row(dz, dy, integral_constant<int, 1>{});
         }
     }
     // the last partial quad: its entries sit in the top (m & 3) words
@@ -986,9 +996,10 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
 //
 // The lanes of a wave hold 64 sources, the targets are taken one at a time:
 // a wave owns 64 consecutive targets (sorted slots) and walks them cell by
-// cell.  For one cell, the sources of its 3^d stencil -- rows in z, y order,
-// per row the fluid slots of its three cells, then their wall slots, the
-// order of the direct search -- form one sequence of S sources held in the
+// cell.  For one cell, the sources of its 3^d stencil -- the fluid slots of
+// the centre row's three cells first (they hold the targets themselves),
+// then the rest in z, y row order, per row the fluid slots of its three
+// cells, then their wall slots -- form one sequence of S sources held in the
 // first nch = ceil(S / 64) of CH register chunks: lane l of chunk j holds
 // element 64 j + l, as its FP32 position p relative to the centre of the
 // target cell, scaled by -2, its |p|^2, and its list entry.  A target t
@@ -1016,12 +1027,13 @@ __device__ __forceinline__ void walk_coop(const SimConst &sc, int k, int m,
 // reach 9 planes.
 template <int DIM, bool SKIN> constexpr int cp_chunks() { return DIM == 3 ? (SKIN ? 10 : 8) : 4; }
 constexpr int kCpListMax = 255;        // list capacity the cell-pair build supports
+constexpr int kNSelf = 2;              // chunks that may hold a target's own entry
 
 // Value of `v` on lane `src` (lane-varying source lane).
 __device__ __forceinline__ int lane_value(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
 
 template <int DIM, bool MIXED, bool SKIN>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_build_cp(
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(SKIN ? 5 : 6))) void k_build_cp(
     SimConst sc, const Chunk *__restrict__ map, const InstDev *__restrict__ inst,
     const int *__restrict__ skey, const int *__restrict__ cstart, const int *__restrict__ wstart,
     const typename Cand<DIM>::t *__restrict__ cpos, uint32_t wcpos_off,
@@ -1081,7 +1093,13 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
     // cell, y, z; each plus one).  The loads are unconditional (a row outside
     // the grid reads the instance's first row and is emptied afterwards), so
     // that they stay in flight until the values are used.
-    const int rrow = lane >> 1, rkind = lane & 1;
+    // Lane 0 describes the centre row's fluid range, which holds every target
+    // of the cell, so that a target's own entry lies in the first kNSelf
+    // chunks and only those need the test against it; lanes 1.. describe the
+    // other ranges in row order.
+    constexpr int RC = NR / 2 - 1;                        // range of the centre row's fluid
+    const int rr = lane == 0 ? RC : (lane <= RC ? lane - 1 : lane);
+    const int rrow = rr >> 1, rkind = rr & 1;
     const int rdy = (DIM == 3 ? rrow % 3 : rrow) - 1;
     const int rdz = DIM == 3 ? rrow / 3 - 1 : 0;
     const int *rst = rkind ? wstart : cstart;
@@ -1193,7 +1211,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
                     float d = fmaf(qx[j], ttx, pp[j]);
                     d = fmaf(qy[j], tty, d);
                     if constexpr (DIM == 3) d = fmaf(qz[j], ttz, d);
-                    const bool near = d < ct, other = ent[j] != eself;
+                    const bool near = d < ct, other = j >= kNSelf || ent[j] != eself;
                     const uint64_t hm = __builtin_amdgcn_ballot_w64(near) & __builtin_amdgcn_ballot_w64(other);
                     int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hm >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0u));
@@ -1213,7 +1231,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5))) 
             }
         };
         using std::integral_constant;
-        if (nch <= CH) {
+        // the cell is built here when its sources fit the chunks and its
+        // centre range the chunks that test the targets' own entries
+        if (nch <= CH && __builtin_amdgcn_readlane(rlen, 0) <= 64 * kNSelf) {
             if constexpr (CH >= 5) {
                 if (nch <= CH - 4) targets(integral_constant<int, CH - 4>{});
                 else if (nch == CH - 3) targets(integral_constant<int, CH - 3>{});
