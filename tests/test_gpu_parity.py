@@ -305,9 +305,9 @@ def test_full_size_c2_against_reference():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_traversal_variants_agree(precision):
-    """Direct search and the neighbour-list sweeps visit the same neighbours in
-    the same order: integers are identical; floats agree
-    to round-off (the compiler may fuse multiply-adds differently per kernel).
+    """Direct search and the neighbour-list sweeps visit the same neighbours
+    (the lists start with the centre row's fluid, the direct search follows the
+    row order): integers are identical; floats agree to round-off.
     A list capacity below the neighbour count takes the overflow path."""
     from paper_2603_11868_amd import sph
     case = dambreak.make_case("tiny_3d")
