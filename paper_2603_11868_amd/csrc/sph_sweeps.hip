@@ -626,8 +626,11 @@ __device__ __forceinline__ void for_neighbours(const SimConst &sc, const InstDev
 // a slot-major list of 16-byte quads, quad q of target k at nlist[q * N + k];
 // its own pair loop and the whole force sweep then walk that list: the force
 // sweep tests no candidates, and a wave reads 1 KiB contiguous per quad.  A
-// target with more than `cap` neighbours walks the stencil instead (same
-// neighbours, same order) and raises SPH_FLAG_CAPACITY.
+// target with more than `cap` neighbours walks the stencil instead (the same
+// neighbours, in the direct search's row order) and raises SPH_FLAG_CAPACITY.
+// A list holds the fluid slots of the target's own stencil row first, then
+// the other rows in z, y order, fluid then wall slots: the nearest sources,
+// whose records sit beside the target's, are gathered first.
 // ---------------------------------------------------------------------------
 
 // Phase 1: candidate tests of target k, hits appended to its list.  Returns the
